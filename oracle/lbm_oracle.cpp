@@ -1,0 +1,482 @@
+// Plain, slow FP64 CPU oracle for the D2Q9 Onsager-regularized lattice Boltzmann step.
+//
+// TEST INFRASTRUCTURE. Only tests/, __graft_entry__.smoke() and bench.py's cpu_baseline
+// leg may load this library. It shares no code, header, table or constant with the HIP
+// path in paper_2602_21242_amd/ and must never be called by it.
+//
+// Every function follows the paper (Jonnalagadda, Rocchia & Succi, "Generalized
+// Onsager-Regularized Lattice Boltzmann Method for error-free Navier-Stokes models on
+// standard lattices", arXiv 2602.21242) step by step, in its order and notation, with no
+// algebraic shortcut: the guided equilibrium is the literal product formula, the OReg
+// population is the literal double sum, the compatibility error and the stress prefactor
+// are moments of the OReg populations, and the corrections are the case formulas.
+// Streaming is the push form of the lattice Boltzmann equation.
+//
+// Readings taken where the paper is terse (each is listed in the design doc):
+//  * tau: the introduction writes tau = nu/theta; with the discrete time step the relation
+//    used here is nu = theta (tau - 1/2), i.e. tau = nu/theta + 1/2 (Sec. 1, eq:lbe; the
+//    (1 - dt/2tau) factors of eq:CEmacroscopicEqs).
+//  * eq:oreg: the population summed under the inner sum is f_k^(neq) (the printed index i
+//    under the sum over k is a typo); D = 2.
+//  * LBGK uses the guided equilibrium (eq:guidedEq) as its equilibrium.
+//  * Complete corrections: for the diagonal links c_{i alpha} c_{i alphabar} = c_ix c_iy.
+//  * The complete model's prefactor is evaluated from the OReg populations, as printed in
+//    eq:geq-prefactor-evaluation.
+//
+// The scalar type is a template parameter so the same literal code runs on
+// std::complex<double>: the adjoint oracle differentiates a step by the complex-step
+// method (the collision is a real rational function of the populations).
+//
+// Layout of every population array: f[i][y][x], i = 0..8 in the numbering of Fig. 1(a),
+// x fastest, no padding. Fields (rho, ux, uy): [y][x].
+
+#include <cmath>
+#include <complex>
+#include <cstdint>
+#include <cstring>
+#include <vector>
+#include <omp.h>
+
+namespace {
+
+using cplx = std::complex<double>;
+
+constexpr int Q = 9;
+constexpr int D = 2;
+
+// Lattice velocities of D2Q9 in the numbering of Fig. 1(a):
+// 0 rest, 1 east, 2 north, 3 west, 4 south, 5 north-east, 6 north-west, 7 south-west,
+// 8 south-east.
+constexpr int c[Q][D] = {{0, 0},  {1, 0},  {0, 1},   {-1, 0}, {0, -1},
+                         {1, 1},  {-1, 1}, {-1, -1}, {1, -1}};
+
+enum Model { BGK = 0, OREG_UC = 1, OREG_PARTIAL = 2, OREG_COMPLETE = 3 };
+
+inline double kron(int a, int b) { return a == b ? 1.0 : 0.0; }
+
+inline double c2(int i) { return double(c[i][0] * c[i][0] + c[i][1] * c[i][1]); }
+
+// Density and velocity: rho = sum_i f_i, rho u_a = sum_i c_ia f_i (Sec. 1, after eq:lbe).
+template <class T>
+void macroscopic_moments(const T f[Q], T& rho, T u[D]) {
+  rho = T(0);
+  for (int i = 0; i < Q; ++i) rho += f[i];
+  for (int a = 0; a < D; ++a) {
+    T m = T(0);
+    for (int i = 0; i < Q; ++i) m += double(c[i][a]) * f[i];
+    u[a] = m / rho;
+  }
+}
+
+// Guided equilibrium, eq:guidedEq:
+// f_i^eq = rho prod_a (1 - 2 c_ia^2) / 2^(c_ia^2) [c_ia^2 - 1 + c_ia u_a + u_a^2 + theta].
+template <class T>
+void guided_equilibrium(T rho, const T u[D], double theta, T feq[Q]) {
+  for (int i = 0; i < Q; ++i) {
+    T prod = rho;
+    for (int a = 0; a < D; ++a) {
+      const double cc = double(c[i][a] * c[i][a]);
+      const double pre = (1.0 - 2.0 * cc) / std::pow(2.0, cc);
+      prod *= pre * (cc - 1.0 + double(c[i][a]) * u[a] + u[a] * u[a] + theta);
+    }
+    feq[i] = prod;
+  }
+}
+
+// Onsager-regularized non-equilibrium population, eq:oreg:
+// f_i^OReg = f_i^eq / (2 rho theta^2) (C_ia C_ib - C_i^2/D delta_ab)
+//            * sum_k (c_ka c_kb - c_k^2/D delta_ab) f_k^neq,   C_i = c_i - u,
+// with f^neq = f - f^eq (Sec. 1) and summation over a, b.
+template <class T>
+void oreg_population(const T f[Q], const T feq[Q], T rho, const T u[D], double theta,
+                     T fo[Q]) {
+  T fneq[Q];
+  for (int k = 0; k < Q; ++k) fneq[k] = f[k] - feq[k];
+  T N[D][D];
+  for (int a = 0; a < D; ++a)
+    for (int b = 0; b < D; ++b) {
+      T s = T(0);
+      for (int k = 0; k < Q; ++k)
+        s += (double(c[k][a] * c[k][b]) - c2(k) / D * kron(a, b)) * fneq[k];
+      N[a][b] = s;
+    }
+  for (int i = 0; i < Q; ++i) {
+    T C[D];
+    for (int a = 0; a < D; ++a) C[a] = double(c[i][a]) - u[a];
+    T Csq = T(0);
+    for (int a = 0; a < D; ++a) Csq += C[a] * C[a];
+    T s = T(0);
+    for (int a = 0; a < D; ++a)
+      for (int b = 0; b < D; ++b) s += (C[a] * C[b] - Csq / double(D) * kron(a, b)) * N[a][b];
+    fo[i] = feq[i] / (2.0 * rho * theta * theta) * s;
+  }
+}
+
+// Compatibility error psi_a = sum_i c_ia f_i^OReg, evaluated directly as the moment
+// (eq:oreg-mom-compatibility; Sec. 3 notes this direct moment is what makes the partial
+// correction local).
+template <class T>
+void compatibility_error(const T fo[Q], T psi[D]) {
+  for (int a = 0; a < D; ++a) {
+    T s = T(0);
+    for (int i = 0; i < Q; ++i) s += double(c[i][a]) * fo[i];
+    psi[a] = s;
+  }
+}
+
+// Prefactor of the stress error, eq:geq-prefactor-evaluation:
+// rho tau/(2 theta) (d_x u_x - d_y u_y) = -1/(4 theta^2) sum_i (c_ix^2 - c_iy^2) f_i^OReg.
+template <class T>
+T stress_prefactor(const T fo[Q], double theta) {
+  T s = T(0);
+  for (int i = 0; i < Q; ++i) s += double(c[i][0] * c[i][0] - c[i][1] * c[i][1]) * fo[i];
+  return -1.0 / (4.0 * theta * theta) * s;
+}
+
+// Stress-tensor error of OReg-GEq, eq:guidedEq-oreg-stress-tensor-error (three cases),
+// given the prefactor. Output Pi[a][b].
+template <class T>
+void stress_error(T pref, const T u[D], double theta, T Pi[D][D]) {
+  const T ux = u[0], uy = u[1];
+  Pi[0][0] = pref * (-(theta * (1.0 - 3.0 * theta) + ux * ux * (ux * ux - 1.0)));
+  Pi[1][1] = pref * (theta * (1.0 - 3.0 * theta) + uy * uy * (uy * uy - 1.0));
+  Pi[0][1] = pref * (ux * uy * (ux * ux - uy * uy));
+  Pi[1][0] = Pi[0][1];
+}
+
+// Axis index of the axis-aligned links in eq:partial-corrections and
+// eq:complete-corrections: x for i in {1,3}, y for i in {2,4}, -1 otherwise.
+inline int link_axis(int i) {
+  if (i == 1 || i == 3) return 0;
+  if (i == 2 || i == 4) return 1;
+  return -1;
+}
+
+// Partially corrected populations, eq:partial-corrections:
+// Psi_i = -1/2 c_ia psi_a on the axis links of axis a, 0 otherwise.
+template <class T>
+void partial_corrections(const T psi[D], T Psi[Q]) {
+  for (int i = 0; i < Q; ++i) {
+    const int a = link_axis(i);
+    Psi[i] = (a < 0) ? T(0) : -0.5 * (double(c[i][a]) * psi[a]);
+  }
+}
+
+// Completely corrected populations, eq:complete-corrections:
+// Psi_i = -1/4 * { 0                                            i = 0
+//                { -2 (Pi_abar abar - c_ia psi_a)                axis links of axis a
+//                { Pi_xx + Pi_yy + c_ix c_iy Pi_xy              diagonal links.
+template <class T>
+void complete_corrections(const T psi[D], const T Pi[D][D], T Psi[Q]) {
+  for (int i = 0; i < Q; ++i) {
+    T bracket;
+    if (i == 0) {
+      bracket = T(0);
+    } else {
+      const int a = link_axis(i);
+      if (a >= 0) {
+        const int abar = 1 - a;
+        bracket = -2.0 * (Pi[abar][abar] - double(c[i][a]) * psi[a]);
+      } else {
+        bracket = Pi[0][0] + Pi[1][1] + double(c[i][0] * c[i][1]) * Pi[0][1];
+      }
+    }
+    Psi[i] = -0.25 * bracket;
+  }
+}
+
+// Diagnostics of one collision, exposed for the oracle's own tests.
+template <class T>
+struct CollisionParts {
+  T rho, u[D], feq[Q], fo[Q], psi[D], pref, Pi[D][D], Psi[Q], fstar[Q];
+};
+
+// Post-collision populations, eq:lbe (first line), with the non-equilibrium part
+//   LBGK:     f^neq = f - f^eq
+//   OReg:     f^OReg                       (eq:oreg)
+//   partial:  f^GOReg = f^OReg + Psi^P     (Sec. 3 and eq:partial-corrections)
+//   complete: f^GOReg = f^OReg + Psi^C     (Sec. 3 and eq:complete-corrections)
+template <class T>
+void collide(const T f[Q], int model, double theta, double tau, CollisionParts<T>& p) {
+  macroscopic_moments(f, p.rho, p.u);
+  guided_equilibrium(p.rho, p.u, theta, p.feq);
+  for (int i = 0; i < Q; ++i) {
+    p.fo[i] = T(0);
+    p.Psi[i] = T(0);
+  }
+  p.psi[0] = p.psi[1] = T(0);
+  p.pref = T(0);
+  for (int a = 0; a < D; ++a)
+    for (int b = 0; b < D; ++b) p.Pi[a][b] = T(0);
+  const double keep = 1.0 - 1.0 / tau;
+  if (model == BGK) {
+    for (int i = 0; i < Q; ++i) p.fstar[i] = p.feq[i] + keep * (f[i] - p.feq[i]);
+    return;
+  }
+  oreg_population(f, p.feq, p.rho, p.u, theta, p.fo);
+  if (model == OREG_PARTIAL || model == OREG_COMPLETE) compatibility_error(p.fo, p.psi);
+  if (model == OREG_PARTIAL) partial_corrections(p.psi, p.Psi);
+  if (model == OREG_COMPLETE) {
+    p.pref = stress_prefactor(p.fo, theta);
+    stress_error(p.pref, p.u, theta, p.Pi);
+    complete_corrections(p.psi, p.Pi, p.Psi);
+  }
+  for (int i = 0; i < Q; ++i) p.fstar[i] = p.feq[i] + keep * (p.fo[i] + p.Psi[i]);
+}
+
+template <class T>
+void collide_only(const T f[Q], int model, double theta, double tau, T fstar[Q]) {
+  CollisionParts<T> p;
+  collide(f, model, theta, tau, p);
+  for (int i = 0; i < Q; ++i) fstar[i] = p.fstar[i];
+}
+
+// Relation between tau and the lattice viscosity (reading of Sec. 1 with dt = 1).
+inline double relaxation_time(double theta, double nu) { return nu / theta + 0.5; }
+
+inline int64_t wrap(int64_t v, int64_t n) { return ((v % n) + n) % n; }
+
+struct Grid {
+  int64_t nx, ny;
+  int64_t nodes() const { return nx * ny; }
+  int64_t at(int i, int64_t y, int64_t x) const { return (int64_t(i) * ny + y) * nx + x; }
+};
+
+// One time step: collide every node, then push each post-collision population to its
+// neighbour, f_i(x + c_i, t + 1) = f_i^*(x, t) (eq:lbe, second line), periodic box.
+void lb_step(const Grid& g, int model, double theta, double tau, const double* f,
+             double* fnew) {
+#pragma omp parallel for schedule(static)
+  for (int64_t y = 0; y < g.ny; ++y) {
+    for (int64_t x = 0; x < g.nx; ++x) {
+      double fl[Q], fs[Q];
+      for (int i = 0; i < Q; ++i) fl[i] = f[g.at(i, y, x)];
+      collide_only(fl, model, theta, tau, fs);
+      for (int i = 0; i < Q; ++i) {
+        const int64_t yd = wrap(y + c[i][1], g.ny), xd = wrap(x + c[i][0], g.nx);
+        fnew[g.at(i, yd, xd)] = fs[i];
+      }
+    }
+  }
+}
+
+// Initial populations f_i = f_i^eq(rho, u) (initialisation reading: start from the guided
+// equilibrium of the given fields).
+template <class T>
+void init_node(T rho, T ux, T uy, double theta, T f[Q]) {
+  T u[D] = {ux, uy};
+  guided_equilibrium(rho, u, theta, f);
+}
+
+// Neumaier-compensated sum accumulator.
+struct Neumaier {
+  double s = 0.0, comp = 0.0;
+  void add(double v) {
+    const double t = s + v;
+    if (std::fabs(s) >= std::fabs(v))
+      comp += (s - t) + v;
+    else
+      comp += (v - t) + s;
+    s = t;
+  }
+  double value() const { return s + comp; }
+};
+
+constexpr double kStep = 1e-30;  // complex-step increment
+
+}  // namespace
+
+extern "C" {
+
+int oracle_num_threads(void) { return omp_get_max_threads(); }
+void oracle_set_num_threads(int n) {
+  if (n > 0) omp_set_num_threads(n);
+}
+
+double oracle_relaxation_time(double theta, double nu) { return relaxation_time(theta, nu); }
+
+// Lattice velocity table (for tests only): cx[9], cy[9].
+void oracle_lattice(int* cx, int* cy) {
+  for (int i = 0; i < Q; ++i) {
+    cx[i] = c[i][0];
+    cy[i] = c[i][1];
+  }
+}
+
+void oracle_guided_equilibrium(double rho, double ux, double uy, double theta, double* feq) {
+  double u[D] = {ux, uy};
+  guided_equilibrium(rho, u, theta, feq);
+}
+
+// Per-node collision with every intermediate quantity, for the oracle's own pins.
+// parts layout (doubles): rho, ux, uy, feq[9], fo[9], psi[2], pref, Pi_xx, Pi_yy, Pi_xy,
+// Psi[9], fstar[9]  -> 3 + 9 + 9 + 2 + 1 + 3 + 9 + 9 = 45 values.
+void oracle_collide_node(const double* f, int model, double theta, double tau, double* parts) {
+  CollisionParts<double> p;
+  collide(f, model, theta, tau, p);
+  double* o = parts;
+  *o++ = p.rho;
+  *o++ = p.u[0];
+  *o++ = p.u[1];
+  for (int i = 0; i < Q; ++i) *o++ = p.feq[i];
+  for (int i = 0; i < Q; ++i) *o++ = p.fo[i];
+  *o++ = p.psi[0];
+  *o++ = p.psi[1];
+  *o++ = p.pref;
+  *o++ = p.Pi[0][0];
+  *o++ = p.Pi[1][1];
+  *o++ = p.Pi[0][1];
+  for (int i = 0; i < Q; ++i) *o++ = p.Psi[i];
+  for (int i = 0; i < Q; ++i) *o++ = p.fstar[i];
+}
+
+// f[9][ny][nx] = f^eq(rho, u) at every node.
+void oracle_init_equilibrium(int64_t nx, int64_t ny, double theta, const double* rho,
+                             const double* ux, const double* uy, double* f) {
+  Grid g{nx, ny};
+#pragma omp parallel for schedule(static)
+  for (int64_t y = 0; y < ny; ++y)
+    for (int64_t x = 0; x < nx; ++x) {
+      double fl[Q];
+      const int64_t n = y * nx + x;
+      init_node(rho[n], ux[n], uy[n], theta, fl);
+      for (int i = 0; i < Q; ++i) f[g.at(i, y, x)] = fl[i];
+    }
+}
+
+// Advance f[9][ny][nx] in place by nsteps time steps.
+void oracle_run(int64_t nx, int64_t ny, double theta, double nu, int model, int64_t nsteps,
+                double* f) {
+  Grid g{nx, ny};
+  const double tau = relaxation_time(theta, nu);
+  std::vector<double> tmp(size_t(Q) * g.nodes());
+  for (int64_t s = 0; s < nsteps; ++s) {
+    lb_step(g, model, theta, tau, f, tmp.data());
+    std::memcpy(f, tmp.data(), sizeof(double) * tmp.size());
+  }
+}
+
+// rho, ux, uy of f at every node.
+void oracle_moments(int64_t nx, int64_t ny, const double* f, double* rho, double* ux,
+                    double* uy) {
+  Grid g{nx, ny};
+#pragma omp parallel for schedule(static)
+  for (int64_t y = 0; y < ny; ++y)
+    for (int64_t x = 0; x < nx; ++x) {
+      double fl[Q], r, u[D];
+      for (int i = 0; i < Q; ++i) fl[i] = f[g.at(i, y, x)];
+      macroscopic_moments(fl, r, u);
+      const int64_t n = y * nx + x;
+      rho[n] = r;
+      ux[n] = u[0];
+      uy[n] = u[1];
+    }
+}
+
+// Total mass and momentum, compensated summation: out[0] = sum rho, out[1..2] = sum rho u.
+void oracle_invariants(int64_t nx, int64_t ny, const double* f, double* out) {
+  Grid g{nx, ny};
+  Neumaier m, jx, jy;
+  for (int64_t y = 0; y < ny; ++y)
+    for (int64_t x = 0; x < nx; ++x)
+      for (int i = 0; i < Q; ++i) {
+        const double v = f[g.at(i, y, x)];
+        m.add(v);
+        jx.add(c[i][0] * v);
+        jy.add(c[i][1] * v);
+      }
+  out[0] = m.value();
+  out[1] = jx.value();
+  out[2] = jy.value();
+}
+
+// Forward map of the differentiable problem: fields at t = 0 -> moments at t = nsteps.
+void oracle_forward_fields(int64_t nx, int64_t ny, double theta, double nu, int model,
+                           int64_t nsteps, const double* rho0, const double* ux0,
+                           const double* uy0, double* rho, double* ux, double* uy) {
+  std::vector<double> f(size_t(Q) * nx * ny);
+  oracle_init_equilibrium(nx, ny, theta, rho0, ux0, uy0, f.data());
+  oracle_run(nx, ny, theta, nu, model, nsteps, f.data());
+  oracle_moments(nx, ny, f.data(), rho, ux, uy);
+}
+
+// One reverse step of the discrete adjoint: given fbar_next = dJ/df^{n+1} (natural layout)
+// and the pre-collision state f^n, return fbar = dJ/df^n. The post-collision adjoint is the
+// reverse-streamed fbar_next, fbar*_i(x) = fbar_next_i(x + c_i); the node Jacobian
+// J_ij = d f*_i / d f_j is taken by the complex-step method, fbar_j = sum_i J_ij fbar*_i.
+void oracle_adjoint_step(int64_t nx, int64_t ny, double theta, double nu, int model,
+                         const double* f, const double* fbar_next, double* fbar) {
+  Grid g{nx, ny};
+  const double tau = relaxation_time(theta, nu);
+#pragma omp parallel for schedule(static)
+  for (int64_t y = 0; y < ny; ++y)
+    for (int64_t x = 0; x < nx; ++x) {
+      double fs_bar[Q];
+      for (int i = 0; i < Q; ++i)
+        fs_bar[i] = fbar_next[g.at(i, wrap(y + c[i][1], ny), wrap(x + c[i][0], nx))];
+      cplx fc[Q], out[Q];
+      for (int j = 0; j < Q; ++j) {
+        for (int k = 0; k < Q; ++k) fc[k] = cplx(f[g.at(k, y, x)], 0.0);
+        fc[j] += cplx(0.0, kStep);
+        collide_only(fc, model, theta, tau, out);
+        double acc = 0.0;
+        for (int i = 0; i < Q; ++i) acc += out[i].imag() / kStep * fs_bar[i];
+        fbar[g.at(j, y, x)] = acc;
+      }
+    }
+}
+
+// Gradient of J with respect to the initial velocity fields (rho0 held fixed), where J
+// depends on the moments at t = nsteps through rho_bar = dJ/drho, ux_bar, uy_bar.
+// Every state f^0..f^nsteps is kept in memory: use at small sizes only.
+void oracle_gradient(int64_t nx, int64_t ny, double theta, double nu, int model,
+                     int64_t nsteps, const double* rho0, const double* ux0, const double* uy0,
+                     const double* rho_bar, const double* ux_bar, const double* uy_bar,
+                     double* ux0_bar, double* uy0_bar) {
+  Grid g{nx, ny};
+  const size_t nf = size_t(Q) * g.nodes();
+  const double tau = relaxation_time(theta, nu);
+  std::vector<double> states(nf * size_t(nsteps + 1));
+  oracle_init_equilibrium(nx, ny, theta, rho0, ux0, uy0, states.data());
+  for (int64_t s = 0; s < nsteps; ++s)
+    lb_step(g, model, theta, tau, states.data() + nf * s, states.data() + nf * (s + 1));
+
+  // Seed: fbar^N_j = rho_bar drho/df_j + u_bar . du/df_j (complex step on the moments).
+  std::vector<double> fbar(nf), fbar_prev(nf);
+  const double* fN = states.data() + nf * nsteps;
+#pragma omp parallel for schedule(static)
+  for (int64_t y = 0; y < ny; ++y)
+    for (int64_t x = 0; x < nx; ++x) {
+      const int64_t n = y * nx + x;
+      for (int j = 0; j < Q; ++j) {
+        cplx fc[Q], r, u[D];
+        for (int k = 0; k < Q; ++k) fc[k] = cplx(fN[g.at(k, y, x)], 0.0);
+        fc[j] += cplx(0.0, kStep);
+        macroscopic_moments(fc, r, u);
+        fbar[g.at(j, y, x)] = rho_bar[n] * r.imag() / kStep + ux_bar[n] * u[0].imag() / kStep +
+                              uy_bar[n] * u[1].imag() / kStep;
+      }
+    }
+  for (int64_t s = nsteps - 1; s >= 0; --s) {
+    oracle_adjoint_step(nx, ny, theta, nu, model, states.data() + nf * s, fbar.data(),
+                        fbar_prev.data());
+    fbar.swap(fbar_prev);
+  }
+  // Initial condition: f^0 = f^eq(rho0, u0); u0_bar_a = sum_i fbar^0_i d f^eq_i / d u_a.
+#pragma omp parallel for schedule(static)
+  for (int64_t y = 0; y < ny; ++y)
+    for (int64_t x = 0; x < nx; ++x) {
+      const int64_t n = y * nx + x;
+      for (int a = 0; a < D; ++a) {
+        cplx uc[D] = {cplx(ux0[n], 0.0), cplx(uy0[n], 0.0)};
+        uc[a] += cplx(0.0, kStep);
+        cplx feq[Q];
+        guided_equilibrium(cplx(rho0[n], 0.0), uc, theta, feq);
+        double acc = 0.0;
+        for (int i = 0; i < Q; ++i) acc += fbar[g.at(i, y, x)] * feq[i].imag() / kStep;
+        (a == 0 ? ux0_bar : uy0_bar)[n] = acc;
+      }
+    }
+}
+
+}  // extern "C"

@@ -1,0 +1,165 @@
+"""Pins of the oracle's full time step against closed forms and invariants.
+
+Streaming direction, conservation, decay of Taylor-Green vortices and shear waves with
+nu = theta (tau - 1/2), Galilean invariance, and the linear decay rate of the normal-stress
+channel at theta != 1/3.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import lbm_inputs as inp
+import oracle
+from tests.lbm_diag import CX, CY, decay_viscosity, field_moments, mode_amplitude
+
+MODELS = ["bgk", "uc", "partial", "complete"]
+
+
+def test_streaming_translates_each_population_along_its_velocity():
+    """With tau -> infinity (1 - 1/tau == 1 in FP64) LBGK leaves populations unchanged, so
+    one step is the push f_i(x + c_i) = f_i(x) of eq:lbe (second line)."""
+    f = inp.random_populations(7, 5, seed=3)
+    g = oracle.run(f, 0.4, 1e300, "bgk", 1)
+    for i in range(9):
+        np.testing.assert_allclose(g[i], np.roll(f[i], (int(CY[i]), int(CX[i])), axis=(0, 1)), rtol=4e-16, atol=0)
+
+
+def test_thread_count_does_not_change_results():
+    f = inp.random_populations(16, 12, seed=4, amp=0.05)
+    n0 = oracle.num_threads()
+    try:
+        oracle.set_num_threads(1)
+        a = oracle.run(f, 0.4, 0.02, "complete", 7)
+        oracle.set_num_threads(max(2, n0))
+        b = oracle.run(f, 0.4, 0.02, "complete", 7)
+    finally:
+        oracle.set_num_threads(n0)
+    assert np.array_equal(a, b)
+
+
+@pytest.fixture(scope="module")
+def tg64_runs():
+    """Taylor-Green 64^2, theta = 1/3, nu = 0.01, U0 = 0.05, noise 1e-3, states at 200 and
+    1000 steps for every model."""
+    rho, ux, uy = inp.taylor_green(64, 64, 0.05, 1 / 3, noise=1e-3, seed=0)
+    f0 = oracle.init_equilibrium(rho, ux, uy, 1 / 3)
+    out = {}
+    for m in MODELS:
+        f200 = oracle.run(f0, 1 / 3, 0.01, m, 200)
+        f1000 = oracle.run(f200, 1 / 3, 0.01, m, 800)
+        out[m] = (f0, f200, f1000)
+    return out
+
+
+@pytest.mark.parametrize("model", MODELS)
+def test_mass_and_momentum_conservation(tg64_runs, model):
+    """Mass is conserved by every model to round-off after 1000 steps; momentum by LBGK,
+    the partially and the completely corrected model (eq:genOReg-constraints), but not by
+    the uncorrected OReg model (eq:CEcontinuity carries psi)."""
+    f0, _, f1 = tg64_runs[model]
+    i0, i1 = oracle.invariants(f0), oracle.invariants(f1)
+    scale = np.sum(np.abs(field_moments(f0)[1])) + np.sum(np.abs(field_moments(f0)[2]))
+    assert abs(i1[0] - i0[0]) / i0[0] < 1e-13
+    dj = np.max(np.abs(i1[1:] - i0[1:])) / scale
+    if model == "uc":
+        assert dj > 1e-9
+    else:
+        assert dj < 1e-13
+
+
+@pytest.mark.parametrize("model,tol", [("bgk", 0.01), ("complete", 0.01), ("partial", 0.03), ("uc", 0.03)])
+def test_taylor_green_decay(tg64_runs, model, tol):
+    """The Taylor-Green mode decays as exp(-nu (kx^2 + ky^2) t) with nu = theta (tau - 1/2).
+    At 64^2 the lattice's O(k^2) error is about 0.7 %; the uncorrected and partial models
+    carry an O(u^2) stress error at this Mach number (eq:guidedEq-oreg-viscosity)."""
+    _, f200, f1000 = tg64_runs[model]
+    k = 2 * math.pi / 64
+    a = [mode_amplitude(field_moments(f)[1], 1, 1) - mode_amplitude(field_moments(f)[1], 1, -1) for f in (f200, f1000)]
+    nu_t = decay_viscosity(a[0], a[1], 2 * k * k, 800)
+    assert abs(nu_t / 0.01 - 1) < tol, nu_t / 0.01
+
+
+def _shear_nu(model, theta, nu, U=(0.0, 0.0), n=64, steps=600, nx=4):
+    rho, ux, uy = inp.shear_wave(nx, n, 1e-3, U)
+    f = oracle.init_equilibrium(rho, ux, uy, theta)
+    f1 = oracle.run(f, theta, nu, model, 100)
+    f2 = oracle.run(f1, theta, nu, model, steps - 100)
+    a1 = mode_amplitude(field_moments(f1)[1], 0, 1)
+    a2 = mode_amplitude(field_moments(f2)[1], 0, 1)
+    k = 2 * math.pi / n
+    return decay_viscosity(a1, a2, k * k, steps - 100)
+
+
+@pytest.mark.parametrize("model", MODELS)
+@pytest.mark.parametrize("theta", [1 / 3, 0.4])
+def test_axis_shear_wave_decay(model, theta):
+    """An axis-aligned shear wave u_x(y) decays as exp(-nu k^2 t) for every model at any
+    theta: the shear stress channel carries no modelling error (mu_xy = 1)."""
+    r = _shear_nu(model, theta, 0.01) / 0.01
+    assert abs(r - 1) < 0.025, r
+
+
+@pytest.mark.parametrize("U", [(0.1, 0.0), (0.0, 0.1), (0.2, 0.0), (0.1 / math.sqrt(2), 0.1 / math.sqrt(2))])
+def test_galilean_invariance_of_complete_model(U):
+    """The completely corrected model is Galilean invariant: advecting the shear wave
+    perpendicular, parallel or diagonally to k leaves its decay rate unchanged."""
+    nu0 = _shear_nu("complete", 0.4, 0.01)
+    nuU = _shear_nu("complete", 0.4, 0.01, U)
+    assert abs(nuU / nu0 - 1) < 1e-3, nuU / nu0
+
+
+def test_uncorrected_model_lacks_galilean_invariance():
+    """At theta != 1/3 the uncorrected OReg model's viscosity depends on the advection
+    velocity (its stress error is O(u), Sec. 2 and eq:guidedEq-oreg-viscosity)."""
+    nu0 = _shear_nu("uc", 0.4, 0.01)
+    nuU = _shear_nu("uc", 0.4, 0.01, (0.2, 0.0))
+    assert nuU / nu0 - 1 > 0.02
+
+
+def _normal_channel_prediction(model, theta, nu):
+    """Linear decay rate of the rotated shear wave (the normal-stress channel N_xx).
+
+    Per step the collision multiplies N_xx by (1 - 1/tau) lam, with lam = 1 (LBGK),
+    mu_xx(u=0) = (1-theta)/(2 theta) (uncorrected and partial), and for the complete
+    model mu_xx(0) minus the stress error of eq:guidedEq-oreg-stress-tensor-error with the
+    prefactor of eq:geq-prefactor-evaluation: (1-theta)(5 theta - 1)/(4 theta^2). The
+    equilibrium produces N_xx at (1-theta)/(2 theta) of the Navier-Stokes rate, because the
+    D2Q9 third moment sum_i c_ix^3 f_i^eq is rho u_x instead of 3 theta rho u_x.
+    """
+    tau = nu / theta + 0.5
+    om = 1 - 1 / tau
+    lam = {"bgk": 1.0, "uc": (1 - theta) / (2 * theta), "partial": (1 - theta) / (2 * theta),
+           "complete": (1 - theta) * (5 * theta - 1) / (4 * theta ** 2)}[model]
+    lam_s = (1 - theta) / (2 * theta)
+    return theta * lam_s * 0.5 * (1 + om * lam) / (1 - om * lam) / nu
+
+
+@pytest.mark.parametrize("model,theta", [("bgk", 0.4), ("complete", 0.4), ("uc", 0.4), ("bgk", 0.5),
+                                         ("complete", 0.5), ("complete", 0.3), ("bgk", 0.3)])
+def test_rotated_shear_wave_normal_stress_channel(model, theta):
+    """Rotated shear wave at rest (64^2, nu = 0.01): the decay rate matches the linear
+    prediction of the normal-stress channel within the O(k^2) error (3 %)."""
+    n, nu = 64, 0.01
+    rho, ux, uy = inp.rotated_shear_wave(n, 1e-4)
+    f = oracle.init_equilibrium(rho, ux, uy, theta)
+    f1 = oracle.run(f, theta, nu, model, 100)
+    f2 = oracle.run(f1, theta, nu, model, 500)
+    amp = lambda g: mode_amplitude(field_moments(g)[1] + field_moments(g)[2], -1, 1)
+    k2 = 2 * (2 * math.pi / n) ** 2
+    r = decay_viscosity(amp(f1), amp(f2), k2, 500) / nu
+    pred = _normal_channel_prediction(model, theta, nu)
+    assert abs(r / pred - 1) < 0.03, (r, pred)
+
+
+def test_partial_model_unstable_at_low_temperature():
+    """theta = 0.3, nu = 0.005: |(1 - 1/tau) mu_xx(0)| > 1 in the normal-stress channel, so
+    the partial model's rotated shear wave grows (the paper reports instabilities of the
+    uncorrected family at theta != 1/3), while the complete model stays bounded."""
+    rho, ux, uy = inp.rotated_shear_wave(32, 1e-6)
+    f = oracle.init_equilibrium(rho, ux, uy, 0.3)
+    fp = oracle.run(f, 0.3, 0.005, "partial", 400)
+    fc = oracle.run(f, 0.3, 0.005, "complete", 400)
+    dev = lambda g: np.max(np.abs(field_moments(g)[1]))
+    assert not np.all(np.isfinite(fp)) or dev(fp) > 1e-3
+    assert dev(fc) < 1e-6
