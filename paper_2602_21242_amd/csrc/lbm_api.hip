@@ -1,0 +1,485 @@
+// Host runtime of liblbm.so: parameter validation, workspace planning, the time-step
+// driver with sqrt(N) checkpointing, the adjoint sweep, and the C ABI declared in lbm.h.
+// Device memory is never allocated here: every buffer lives in the caller's workspace.
+#include "lbm.h"
+
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdlib>
+#include <cstring>
+#include <exception>
+#include <new>
+#include <string>
+
+#include "lbm_engine.h"
+
+namespace lbm {
+extern template struct Engine<double>;
+extern template struct Engine<float>;
+extern template struct Engine<_Float16>;
+extern template struct Engine<bf16_t>;
+}  // namespace lbm
+
+namespace {
+
+thread_local std::string g_last_error;
+
+lbm_status fail(lbm_status s, const std::string& msg) {
+  g_last_error = msg;
+  return s;
+}
+
+size_t round_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
+
+size_t storage_size(int dt) { return dt == LBM_F64 ? 8 : dt == LBM_F32 ? 4 : 2; }
+
+// Workspace regions (byte offsets into the caller's buffer).
+struct Plan {
+  size_t esize = 0, tsize = 0;        // storage / compute element sizes
+  size_t plane_bytes = 0, plane_t_bytes = 0;
+  size_t pop_bytes = 0;               // one set of nine planes (storage type)
+  size_t pop_off[2] = {0, 0};
+  size_t red_off = 0, res_off = 0;
+  int64_t stride = 0;                 // checkpoint spacing s
+  int64_t nck = 0;                    // checkpoints at t = 0, s, 2s, ... (< N)
+  size_t ckpt_off = 0;                // nck + 1 slots (the last holds the state at t = N)
+  size_t rec_off = 0, rec_slot_bytes = 0;
+  size_t fbar_off[2] = {0, 0}, fbar_bytes = 0;
+  size_t total = 0;
+};
+
+lbm_status validate(const lbm_params* p) {
+  if (!p) return fail(LBM_ERR_INVALID_ARGUMENT, "params is NULL");
+  if (p->nx < 1 || p->ny < 1) return fail(LBM_ERR_INVALID_ARGUMENT, "nx and ny must be >= 1");
+  const int64_t pitch = (int64_t(p->nx) + 7) / 8 * 8;
+  if (pitch * int64_t(p->ny) >= (int64_t(1) << 31))
+    return fail(LBM_ERR_INVALID_ARGUMENT, "grid too large: padded plane must hold < 2^31 nodes");
+  if (!(p->theta > 0.0 && p->theta < 1.0)) return fail(LBM_ERR_INVALID_ARGUMENT, "theta must lie in (0, 1)");
+  if (!(p->nu > 0.0) || !std::isfinite(p->nu)) return fail(LBM_ERR_INVALID_ARGUMENT, "nu must be finite and > 0");
+  if (!(p->rho0 > 0.0) || !std::isfinite(p->rho0)) return fail(LBM_ERR_INVALID_ARGUMENT, "rho0 must be finite and > 0");
+  if (p->model < LBM_BGK || p->model > LBM_OREG_COMPLETE) return fail(LBM_ERR_INVALID_ARGUMENT, "unknown model");
+  if (p->storage < LBM_F64 || p->storage > LBM_F16) return fail(LBM_ERR_INVALID_ARGUMENT, "unknown storage type");
+  if (p->pattern != LBM_AB && p->pattern != LBM_AA) return fail(LBM_ERR_INVALID_ARGUMENT, "unknown pattern");
+  if (p->record_steps < 0) return fail(LBM_ERR_INVALID_ARGUMENT, "record_steps must be >= 0");
+  if (p->ckpt_stride < 0) return fail(LBM_ERR_INVALID_ARGUMENT, "ckpt_stride must be >= 0");
+  return LBM_OK;
+}
+
+Plan make_plan(const lbm_params& p) {
+  Plan pl;
+  pl.esize = storage_size(p.storage);
+  pl.tsize = p.storage == LBM_F64 ? 8 : 4;
+  const size_t pitch = (size_t(p.nx) + 7) / 8 * 8;
+  // Planes are 4 KiB multiples plus a 512-byte stagger so that the nine streams of one
+  // step do not start on the same HBM channel.
+  pl.plane_bytes = round_up(pitch * p.ny * pl.esize, 4096) + 512;
+  pl.plane_t_bytes = round_up(pitch * p.ny * pl.tsize, 4096) + 512;
+  pl.pop_bytes = lbm::Q * pl.plane_bytes;
+  size_t off = 0;
+  pl.pop_off[0] = off;
+  off += pl.pop_bytes;
+  if (p.pattern == LBM_AB) {
+    pl.pop_off[1] = off;
+    off += pl.pop_bytes;
+  }
+  pl.red_off = off;
+  off += round_up(lbm::kReduceBlocks * 4 * sizeof(double), 256);
+  pl.res_off = off;
+  off += 256;
+  if (p.record_steps > 0) {
+    const int64_t N = p.record_steps;
+    pl.stride = p.ckpt_stride > 0 ? p.ckpt_stride : int64_t(std::ceil(std::sqrt(double(N))));
+    if (pl.stride < 1) pl.stride = 1;
+    pl.nck = (N + pl.stride - 1) / pl.stride;
+    pl.ckpt_off = off;
+    off += size_t(pl.nck + 1) * pl.pop_bytes;
+    pl.rec_slot_bytes = lbm::NREC * pl.plane_t_bytes;
+    pl.rec_off = off;
+    off += size_t(pl.stride) * pl.rec_slot_bytes;
+    pl.fbar_bytes = lbm::Q * pl.plane_t_bytes;
+    pl.fbar_off[0] = off;
+    off += pl.fbar_bytes;
+    pl.fbar_off[1] = off;
+    off += pl.fbar_bytes;
+  }
+  pl.total = off;
+  return pl;
+}
+
+struct DeviceGuard {
+  int prev = -1;
+  explicit DeviceGuard(int dev) {
+    if (hipGetDevice(&prev) == hipSuccess && prev != dev) (void)hipSetDevice(dev);
+    else prev = -1;
+  }
+  ~DeviceGuard() {
+    if (prev >= 0) (void)hipSetDevice(prev);
+  }
+};
+
+}  // namespace
+
+struct lbm_ctx {
+  lbm_params p;
+  lbm::RunDesc d;
+  Plan plan;
+  char* ws = nullptr;
+  hipStream_t stream = nullptr;
+  int device = 0;
+  int64_t time = 0;
+  int cur = 0;            // A-B: buffer holding the state
+  bool rec_valid = false; // recorded run usable by the adjoint
+
+  void* state() const { return ws + plan.pop_off[p.pattern == LBM_AB ? cur : 0]; }
+  lbm::LayoutSel layout(int64_t t) const {
+    if (p.pattern == LBM_AB) return {1, 0};
+    return (t & 1) ? lbm::LayoutSel{1, 1} : lbm::LayoutSel{0, 0};
+  }
+  void* ckpt(int64_t k) const { return ws + plan.ckpt_off + size_t(k) * plan.pop_bytes; }
+  void* rec_slot(int64_t j) const { return ws + plan.rec_off + size_t(j) * plan.rec_slot_bytes; }
+  void* fbar(int b) const { return ws + plan.fbar_off[b]; }
+};
+
+namespace {
+
+#define HIP_TRY(expr)                                                                          \
+  do {                                                                                         \
+    hipError_t e_ = (expr);                                                                    \
+    if (e_ != hipSuccess) return fail(LBM_ERR_HIP, std::string(#expr) + ": " + hipGetErrorString(e_)); \
+  } while (0)
+
+template <class F>
+lbm_status dispatch(int storage, F&& f) {
+  switch (storage) {
+    case LBM_F64: return f(lbm::Engine<double>{});
+    case LBM_F32: return f(lbm::Engine<float>{});
+    case LBM_F16: return f(lbm::Engine<_Float16>{});
+    default: return f(lbm::Engine<lbm::bf16_t>{});
+  }
+}
+
+lbm_status check_ctx(const lbm_ctx* c) {
+  if (!c) return fail(LBM_ERR_INVALID_ARGUMENT, "context is NULL");
+  return LBM_OK;
+}
+
+// One time step of the current pattern; rec != nullptr also writes the moment record.
+lbm_status do_step(lbm_ctx* c, void* rec) {
+  return dispatch(c->p.storage, [&](auto eng) -> lbm_status {
+    using E = decltype(eng);
+    hipError_t e;
+    if (c->p.pattern == LBM_AB) {
+      e = E::step(c->d, lbm::PH_AB, c->ws + c->plan.pop_off[c->cur], c->ws + c->plan.pop_off[1 - c->cur], rec,
+                  c->stream);
+      if (e == hipSuccess) c->cur ^= 1;
+    } else {
+      const int ph = (c->time & 1) ? lbm::PH_AA_ODD : lbm::PH_AA_EVEN;
+      e = E::step(c->d, ph, c->ws + c->plan.pop_off[0], c->ws + c->plan.pop_off[0], rec, c->stream);
+    }
+    if (e != hipSuccess) return fail(LBM_ERR_HIP, std::string("step kernel launch: ") + hipGetErrorString(e));
+    ++c->time;
+    return LBM_OK;
+  });
+}
+
+lbm_status restore(lbm_ctx* c, int64_t slot, int64_t t) {
+  HIP_TRY(hipMemcpyAsync(c->ws + c->plan.pop_off[0], c->ckpt(slot), c->plan.pop_bytes, hipMemcpyDeviceToDevice, c->stream));
+  c->cur = 0;
+  c->time = t;
+  return LBM_OK;
+}
+
+// Reverse sweep over the recorded run: on entry fbar(0) holds dJ/df^N; on exit fbar(*out_b)
+// holds dJ/df^0. Segment k (steps [k s, min((k+1) s, N))) is recomputed from its checkpoint
+// while recording moments, then traversed backwards with the adjoint kernel.
+lbm_status sweep(lbm_ctx* c, int* out_b) {
+  const int64_t N = c->p.record_steps, s = c->plan.stride;
+  int b = 0;
+  for (int64_t k = c->plan.nck - 1; k >= 0; --k) {
+    const int64_t t0 = k * s, t1 = std::min(t0 + s, N);
+    lbm_status st = restore(c, k, t0);
+    if (st != LBM_OK) return st;
+    for (int64_t t = t0; t < t1; ++t) {
+      st = do_step(c, c->rec_slot(t - t0));
+      if (st != LBM_OK) return st;
+    }
+    for (int64_t t = t1 - 1; t >= t0; --t) {
+      st = dispatch(c->p.storage, [&](auto eng) -> lbm_status {
+        using E = decltype(eng);
+        using T = typename E::T;
+        hipError_t e = E::adjoint_step(c->d, static_cast<const T*>(c->fbar(b)), static_cast<T*>(c->fbar(1 - b)),
+                                       static_cast<const T*>(c->rec_slot(t - t0)), c->stream);
+        if (e != hipSuccess) return fail(LBM_ERR_HIP, std::string("adjoint kernel launch: ") + hipGetErrorString(e));
+        return LBM_OK;
+      });
+      if (st != LBM_OK) return st;
+      b ^= 1;
+    }
+  }
+  *out_b = b;
+  return LBM_OK;
+}
+
+lbm_status check_adjoint_ready(const lbm_ctx* c) {
+  if (c->p.record_steps <= 0) return fail(LBM_ERR_STATE, "context was created with record_steps = 0");
+  if (!c->rec_valid) return fail(LBM_ERR_STATE, "recorded run was invalidated by lbm_set_populations");
+  if (c->time != c->p.record_steps)
+    return fail(LBM_ERR_STATE, "lbm_time must equal record_steps (" + std::to_string(c->p.record_steps) + "), is " +
+                                   std::to_string(c->time));
+  return LBM_OK;
+}
+
+template <class F>
+lbm_status guarded(F&& f) {
+  try {
+    return f();
+  } catch (const std::bad_alloc&) {
+    return fail(LBM_ERR_INVALID_ARGUMENT, "host allocation failed");
+  } catch (const std::exception& e) {
+    return fail(LBM_ERR_INVALID_ARGUMENT, e.what());
+  } catch (...) {
+    return fail(LBM_ERR_INVALID_ARGUMENT, "unknown exception");
+  }
+}
+
+int default_vec(size_t esize) {
+  int v = int(16 / esize);
+  if (const char* s = std::getenv("LBM_VEC")) {
+    const int w = std::atoi(s);
+    if (w > 0) v = w;
+  }
+  return v;
+}
+
+}  // namespace
+
+extern "C" {
+
+lbm_status lbm_workspace_bytes(const lbm_params* p, size_t* bytes) {
+  return guarded([&]() -> lbm_status {
+    lbm_status s = validate(p);
+    if (s != LBM_OK) return s;
+    if (!bytes) return fail(LBM_ERR_INVALID_ARGUMENT, "bytes is NULL");
+    *bytes = make_plan(*p).total;
+    return LBM_OK;
+  });
+}
+
+lbm_status lbm_init(const lbm_params* p, void* d_workspace, size_t workspace_bytes, void* hip_stream,
+                    const double* d_rho, const double* d_ux, const double* d_uy, lbm_ctx** out) {
+  return guarded([&]() -> lbm_status {
+    if (!out) return fail(LBM_ERR_INVALID_ARGUMENT, "out is NULL");
+    *out = nullptr;
+    lbm_status s = validate(p);
+    if (s != LBM_OK) return s;
+    if (!d_workspace) return fail(LBM_ERR_INVALID_ARGUMENT, "workspace is NULL");
+    if (reinterpret_cast<uintptr_t>(d_workspace) % 256 != 0)
+      return fail(LBM_ERR_INVALID_ARGUMENT, "workspace must be 256-byte aligned");
+    if (!d_ux || !d_uy) return fail(LBM_ERR_INVALID_ARGUMENT, "velocity fields are required");
+    const Plan plan = make_plan(*p);
+    if (workspace_bytes < plan.total)
+      return fail(LBM_ERR_WORKSPACE_TOO_SMALL, "workspace has " + std::to_string(workspace_bytes) + " bytes, needs " +
+                                                   std::to_string(plan.total));
+    lbm_ctx* c = new lbm_ctx();
+    c->p = *p;
+    c->plan = plan;
+    c->ws = static_cast<char*>(d_workspace);
+    c->stream = static_cast<hipStream_t>(hip_stream);
+    if (hipGetDevice(&c->device) != hipSuccess) c->device = 0;
+    lbm::RunDesc& d = c->d;
+    d.nx = p->nx;
+    d.ny = p->ny;
+    d.pitch = int((p->nx + 7) / 8 * 8);
+    d.plane = int64_t(plan.plane_bytes / plan.esize);
+    d.plane_t = int64_t(plan.plane_t_bytes / plan.tsize);
+    d.theta = p->theta;
+    d.nu = p->nu;
+    d.rho0 = p->rho0;
+    d.tau = p->nu / p->theta + 0.5;  // nu = theta (tau - 1/2)
+    d.model = p->model;
+    d.vec = default_vec(plan.esize);
+    c->time = 0;
+    c->cur = 0;
+    c->rec_valid = p->record_steps > 0;
+    s = dispatch(p->storage, [&](auto eng) -> lbm_status {
+      using E = decltype(eng);
+      hipError_t e = E::init(c->d, c->layout(0), c->state(), d_rho, d_ux, d_uy, c->stream);
+      if (e != hipSuccess) return fail(LBM_ERR_HIP, std::string("init kernel launch: ") + hipGetErrorString(e));
+      return LBM_OK;
+    });
+    if (s != LBM_OK) {
+      delete c;
+      return s;
+    }
+    *out = c;
+    return LBM_OK;
+  });
+}
+
+lbm_status lbm_step(lbm_ctx* c, int64_t n) {
+  return guarded([&]() -> lbm_status {
+    lbm_status s = check_ctx(c);
+    if (s != LBM_OK) return s;
+    if (n < 0) return fail(LBM_ERR_INVALID_ARGUMENT, "n must be >= 0");
+    DeviceGuard g(c->device);
+    const int64_t N = c->p.record_steps;
+    for (int64_t k = 0; k < n; ++k) {
+      if (N > 0 && c->rec_valid && c->time < N && c->time % c->plan.stride == 0)
+        HIP_TRY(hipMemcpyAsync(c->ckpt(c->time / c->plan.stride), c->state(), c->plan.pop_bytes,
+                               hipMemcpyDeviceToDevice, c->stream));
+      s = do_step(c, nullptr);
+      if (s != LBM_OK) return s;
+    }
+    return LBM_OK;
+  });
+}
+
+lbm_status lbm_moments(lbm_ctx* c, lbm_dtype out_dtype, void* d_rho, void* d_ux, void* d_uy) {
+  return guarded([&]() -> lbm_status {
+    lbm_status s = check_ctx(c);
+    if (s != LBM_OK) return s;
+    if (out_dtype != LBM_F64 && out_dtype != LBM_F32) return fail(LBM_ERR_UNSUPPORTED, "moments: output must be F64 or F32");
+    DeviceGuard g(c->device);
+    return dispatch(c->p.storage, [&](auto eng) -> lbm_status {
+      using E = decltype(eng);
+      hipError_t e = E::moments(c->d, c->layout(c->time), c->state(), out_dtype == LBM_F64, d_rho, d_ux, d_uy, c->stream);
+      if (e != hipSuccess) return fail(LBM_ERR_HIP, std::string("moments kernel launch: ") + hipGetErrorString(e));
+      return LBM_OK;
+    });
+  });
+}
+
+lbm_status lbm_get_populations(lbm_ctx* c, lbm_dtype out_dtype, void* d_f) {
+  return guarded([&]() -> lbm_status {
+    lbm_status s = check_ctx(c);
+    if (s != LBM_OK) return s;
+    if (!d_f) return fail(LBM_ERR_INVALID_ARGUMENT, "output is NULL");
+    if (out_dtype != LBM_F64 && out_dtype != LBM_F32) return fail(LBM_ERR_UNSUPPORTED, "populations: output must be F64 or F32");
+    DeviceGuard g(c->device);
+    return dispatch(c->p.storage, [&](auto eng) -> lbm_status {
+      using E = decltype(eng);
+      hipError_t e = E::get(c->d, c->layout(c->time), c->state(), out_dtype == LBM_F64, d_f, c->stream);
+      if (e != hipSuccess) return fail(LBM_ERR_HIP, std::string("export kernel launch: ") + hipGetErrorString(e));
+      return LBM_OK;
+    });
+  });
+}
+
+lbm_status lbm_set_populations(lbm_ctx* c, const double* d_f) {
+  return guarded([&]() -> lbm_status {
+    lbm_status s = check_ctx(c);
+    if (s != LBM_OK) return s;
+    if (!d_f) return fail(LBM_ERR_INVALID_ARGUMENT, "input is NULL");
+    DeviceGuard g(c->device);
+    if (c->time != 0) c->rec_valid = false;
+    return dispatch(c->p.storage, [&](auto eng) -> lbm_status {
+      using E = decltype(eng);
+      hipError_t e = E::set(c->d, c->layout(c->time), c->state(), d_f, c->stream);
+      if (e != hipSuccess) return fail(LBM_ERR_HIP, std::string("import kernel launch: ") + hipGetErrorString(e));
+      return LBM_OK;
+    });
+  });
+}
+
+lbm_status lbm_invariants(lbm_ctx* c, double out[3]) {
+  return guarded([&]() -> lbm_status {
+    lbm_status s = check_ctx(c);
+    if (s != LBM_OK) return s;
+    if (!out) return fail(LBM_ERR_INVALID_ARGUMENT, "out is NULL");
+    DeviceGuard g(c->device);
+    double* partial = reinterpret_cast<double*>(c->ws + c->plan.red_off);
+    double* result = reinterpret_cast<double*>(c->ws + c->plan.res_off);
+    s = dispatch(c->p.storage, [&](auto eng) -> lbm_status {
+      using E = decltype(eng);
+      hipError_t e = E::invariants(c->d, c->layout(c->time), c->state(), partial, result, c->stream);
+      if (e != hipSuccess) return fail(LBM_ERR_HIP, std::string("reduction kernel launch: ") + hipGetErrorString(e));
+      return LBM_OK;
+    });
+    if (s != LBM_OK) return s;
+    double host[4];
+    HIP_TRY(hipMemcpyAsync(host, result, sizeof(host), hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(hipStreamSynchronize(c->stream));
+    out[0] = host[0];
+    out[1] = host[1];
+    out[2] = host[2];
+    if (host[3] > 0.0) return fail(LBM_ERR_NONFINITE, std::to_string(int64_t(host[3])) + " nodes hold non-finite populations");
+    return LBM_OK;
+  });
+}
+
+lbm_status lbm_adjoint(lbm_ctx* c, const void* d_rho_bar, const void* d_ux_bar, const void* d_uy_bar,
+                       void* d_ux0_bar, void* d_uy0_bar) {
+  return guarded([&]() -> lbm_status {
+    lbm_status s = check_ctx(c);
+    if (s != LBM_OK) return s;
+    s = check_adjoint_ready(c);
+    if (s != LBM_OK) return s;
+    if (!d_ux_bar || !d_uy_bar || !d_ux0_bar || !d_uy0_bar)
+      return fail(LBM_ERR_INVALID_ARGUMENT, "adjoint: velocity adjoint pointers are required");
+    DeviceGuard g(c->device);
+    const int64_t N = c->p.record_steps;
+    HIP_TRY(hipMemcpyAsync(c->ckpt(c->plan.nck), c->state(), c->plan.pop_bytes, hipMemcpyDeviceToDevice, c->stream));
+    return dispatch(c->p.storage, [&](auto eng) -> lbm_status {
+      using E = decltype(eng);
+      using T = typename E::T;
+      hipError_t e = E::seed(c->d, c->layout(N), c->state(), static_cast<const T*>(d_rho_bar),
+                             static_cast<const T*>(d_ux_bar), static_cast<const T*>(d_uy_bar),
+                             static_cast<T*>(c->fbar(0)), c->stream);
+      if (e != hipSuccess) return fail(LBM_ERR_HIP, std::string("seed kernel launch: ") + hipGetErrorString(e));
+      int b = 0;
+      lbm_status st = sweep(c, &b);
+      if (st != LBM_OK) return st;
+      e = E::ic_adjoint(c->d, c->layout(0), c->ckpt(0), static_cast<const T*>(c->fbar(b)), static_cast<T*>(d_ux0_bar),
+                        static_cast<T*>(d_uy0_bar), c->stream);
+      if (e != hipSuccess) return fail(LBM_ERR_HIP, std::string("initial-condition adjoint launch: ") + hipGetErrorString(e));
+      return restore(c, c->plan.nck, N);
+    });
+  });
+}
+
+lbm_status lbm_adjoint_populations(lbm_ctx* c, const void* d_fbarN, void* d_fbar0) {
+  return guarded([&]() -> lbm_status {
+    lbm_status s = check_ctx(c);
+    if (s != LBM_OK) return s;
+    s = check_adjoint_ready(c);
+    if (s != LBM_OK) return s;
+    if (!d_fbarN || !d_fbar0) return fail(LBM_ERR_INVALID_ARGUMENT, "adjoint: population pointers are required");
+    DeviceGuard g(c->device);
+    const int64_t N = c->p.record_steps;
+    HIP_TRY(hipMemcpyAsync(c->ckpt(c->plan.nck), c->state(), c->plan.pop_bytes, hipMemcpyDeviceToDevice, c->stream));
+    return dispatch(c->p.storage, [&](auto eng) -> lbm_status {
+      using E = decltype(eng);
+      using T = typename E::T;
+      hipError_t e = E::fbar_import(c->d, static_cast<const T*>(d_fbarN), static_cast<T*>(c->fbar(0)), c->stream);
+      if (e != hipSuccess) return fail(LBM_ERR_HIP, std::string("adjoint import launch: ") + hipGetErrorString(e));
+      int b = 0;
+      lbm_status st = sweep(c, &b);
+      if (st != LBM_OK) return st;
+      e = E::fbar_export(c->d, static_cast<const T*>(c->fbar(b)), static_cast<T*>(d_fbar0), c->stream);
+      if (e != hipSuccess) return fail(LBM_ERR_HIP, std::string("adjoint export launch: ") + hipGetErrorString(e));
+      return restore(c, c->plan.nck, N);
+    });
+  });
+}
+
+int64_t lbm_time(const lbm_ctx* c) { return c ? c->time : -1; }
+
+const char* lbm_status_string(lbm_status s) {
+  switch (s) {
+    case LBM_OK: return "LBM_OK";
+    case LBM_ERR_INVALID_ARGUMENT: return "LBM_ERR_INVALID_ARGUMENT";
+    case LBM_ERR_UNSUPPORTED: return "LBM_ERR_UNSUPPORTED";
+    case LBM_ERR_WORKSPACE_TOO_SMALL: return "LBM_ERR_WORKSPACE_TOO_SMALL";
+    case LBM_ERR_HIP: return "LBM_ERR_HIP";
+    case LBM_ERR_NONFINITE: return "LBM_ERR_NONFINITE";
+    case LBM_ERR_STATE: return "LBM_ERR_STATE";
+  }
+  return "LBM_ERR_UNKNOWN";
+}
+
+const char* lbm_last_error(void) { return g_last_error.c_str(); }
+
+void lbm_destroy(lbm_ctx* c) { delete c; }
+
+}  // extern "C"

@@ -1,0 +1,74 @@
+// Host-callable launchers for one storage type S (explicitly instantiated in
+// step_<type>.hip) plus the auxiliary per-node kernels: initialisation at the guided
+// equilibrium, population export/import, moments, FP64 invariants, and the adjoint's
+// seed and initial-condition kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "lbm_device.h"
+
+namespace lbm {
+
+// Everything a launcher needs to know about a run (host side).
+struct RunDesc {
+  int nx, ny, pitch;
+  int64_t plane;     // storage-type elements between population planes
+  int64_t plane_t;   // compute-type elements between planes of fbar and of recorded moments
+  double theta, nu, rho0, tau;
+  int model;         // M_BGK ... M_COMPLETE
+  int vec;           // nodes per thread of the step and adjoint kernels
+};
+
+// State layout at a given time: f_i(x) = buf[swap ? opp(i) : i][x - shift c_i].
+struct LayoutSel {
+  int shift, swap;
+};
+
+constexpr int kReduceBlocks = 1024;  // partial sums of the FP64 invariants
+
+template <class S>
+struct Engine {
+  using T = typename StorageTraits<S>::T;
+  static hipError_t step(const RunDesc& d, int phase, const void* src, void* dst, void* rec, hipStream_t st);
+  static hipError_t init(const RunDesc& d, LayoutSel L, void* buf, const double* rho, const double* ux,
+                         const double* uy, hipStream_t st);
+  static hipError_t get(const RunDesc& d, LayoutSel L, const void* buf, bool out_f64, void* out, hipStream_t st);
+  static hipError_t set(const RunDesc& d, LayoutSel L, void* buf, const double* in, hipStream_t st);
+  static hipError_t moments(const RunDesc& d, LayoutSel L, const void* buf, bool out_f64, void* rho, void* ux,
+                            void* uy, hipStream_t st);
+  static hipError_t invariants(const RunDesc& d, LayoutSel L, const void* buf, double* partial, double* result,
+                               hipStream_t st);
+  static hipError_t seed(const RunDesc& d, LayoutSel L, const void* buf, const T* rhob, const T* uxb,
+                         const T* uyb, T* fbar, hipStream_t st);
+  static hipError_t fbar_import(const RunDesc& d, const T* dense, T* fbar, hipStream_t st);
+  static hipError_t fbar_export(const RunDesc& d, const T* fbar, T* dense, hipStream_t st);
+  static hipError_t adjoint_step(const RunDesc& d, const T* fbar_next, T* fbar, const T* rec, hipStream_t st);
+  static hipError_t ic_adjoint(const RunDesc& d, LayoutSel L, const void* buf0, const T* fbar, T* uxb, T* uyb,
+                               hipStream_t st);
+};
+
+// Host-side construction of the per-run constants (FP64, rounded once to T).
+template <class T>
+inline Coef<T> make_coef(const RunDesc& d) {
+  Coef<T> k;
+  const double th = d.theta;
+  k.rho0 = T(d.rho0);
+  k.omb = T(1.0 - 1.0 / d.tau);
+  k.r0 = T(1.0 - th);
+  k.r1 = T(0.5 * th);
+  k.rr0 = T(d.rho0 * (1.0 - th));
+  k.rr1 = T(d.rho0 * 0.5 * th);
+  k.inv2th2 = T(1.0 / (2.0 * th * th));
+  k.inv4th2 = T(1.0 / (4.0 * th * th));
+  k.a0 = T(th * (1.0 - 3.0 * th));
+  for (int i = 0; i < Q; ++i) {
+    const double rx = cx(i) == 0 ? 1.0 - th : 0.5 * th;
+    const double ry = cy(i) == 0 ? 1.0 - th : 0.5 * th;
+    k.wr[i] = T(rx * ry * d.rho0);
+  }
+  return k;
+}
+
+}  // namespace lbm

@@ -1,0 +1,394 @@
+// Definitions of Engine<S> (see lbm_engine.h). Included once per storage type.
+#pragma once
+
+#include "lbm_engine.h"
+#include "lbm_step.h"
+
+namespace lbm {
+
+// --- geometry -----------------------------------------------------------------------------
+
+inline Geo make_geo(const RunDesc& d, int vec, int64_t plane) {
+  Geo g;
+  g.nx = d.nx;
+  g.ny = d.ny;
+  g.pitch = d.pitch;
+  g.plane = plane;
+  g.ngx = (d.nx + vec - 1) / vec;
+  g.ngroups = g.ngx * d.ny;
+  g.nblocks = (g.ngroups + kBlock - 1) / kBlock;
+  g.nb8 = (g.nblocks + 7) / 8;
+  return g;
+}
+
+inline dim3 step_grid(const Geo& g) { return dim3(unsigned(8 * g.nb8)); }
+
+inline int node_blocks(const RunDesc& d) { return int((int64_t(d.nx) * d.ny + kBlock - 1) / kBlock); }
+
+__device__ __forceinline__ int64_t layout_index(int i, int x, int y, int nx, int ny, int pitch, int64_t plane,
+                                                LayoutSel L) {
+  const int slot = L.swap ? opp(i) : i;
+  int xs = x - L.shift * cx(i);
+  xs = xs < 0 ? xs + nx : (xs >= nx ? xs - nx : xs);
+  int ys = y - L.shift * cy(i);
+  ys = ys < 0 ? ys + ny : (ys >= ny ? ys - ny : ys);
+  return int64_t(slot) * plane + int64_t(ys) * pitch + xs;
+}
+
+// --- per-node auxiliary kernels --------------------------------------------------------------
+
+// f^0 = f^eq(rho, u) of the guided equilibrium (eq:guidedEq), stored shifted, computed in FP64
+// as drho Phi_x Phi_y + rho0 (d_x Phi_y + r_x d_y) (no cancellation against w_i rho0).
+template <class S>
+__global__ void __launch_bounds__(kBlock)
+k_init(S* buf, RunDesc d, LayoutSel L, const double* rho, const double* ux, const double* uy) {
+  using Tr = StorageTraits<S>;
+  const int64_t n = int64_t(blockIdx.x) * kBlock + threadIdx.x;
+  if (n >= int64_t(d.nx) * d.ny) return;
+  const int y = int(n / d.nx), x = int(n - int64_t(y) * d.nx);
+  const double r = rho ? rho[n] : d.rho0;
+  const double vx = ux[n], vy = uy[n];
+  const double drho = r - d.rho0;
+  const double th = d.theta;
+  const double dx[3] = {0.5 * (vx * vx - vx), -vx * vx, 0.5 * (vx * vx + vx)};
+  const double dy[3] = {0.5 * (vy * vy - vy), -vy * vy, 0.5 * (vy * vy + vy)};
+  const double rr[3] = {0.5 * th, 1.0 - th, 0.5 * th};
+#pragma unroll
+  for (int i = 0; i < Q; ++i) {
+    const int a = cx(i) + 1, b = cy(i) + 1;
+    const double hx = rr[a] + dx[a], hy = rr[b] + dy[b];
+    const double feqs = drho * hx * hy + d.rho0 * (dx[a] * hy + rr[a] * dy[b]);
+    buf[layout_index(i, x, y, d.nx, d.ny, d.pitch, d.plane, L)] = Tr::store(typename Tr::T(feqs));
+  }
+}
+
+template <class S, class O>
+__global__ void __launch_bounds__(kBlock)
+k_get(const S* buf, RunDesc d, LayoutSel L, O* out) {
+  using Tr = StorageTraits<S>;
+  const int64_t N = int64_t(d.nx) * d.ny;
+  const int64_t n = int64_t(blockIdx.x) * kBlock + threadIdx.x;
+  if (n >= N) return;
+  const int y = int(n / d.nx), x = int(n - int64_t(y) * d.nx);
+  const double th = d.theta;
+#pragma unroll
+  for (int i = 0; i < Q; ++i) {
+    const double w = (cx(i) == 0 ? 1.0 - th : 0.5 * th) * (cy(i) == 0 ? 1.0 - th : 0.5 * th);
+    const double g = double(Tr::load(buf[layout_index(i, x, y, d.nx, d.ny, d.pitch, d.plane, L)]));
+    out[i * N + n] = O(g + w * d.rho0);
+  }
+}
+
+template <class S>
+__global__ void __launch_bounds__(kBlock)
+k_set(S* buf, RunDesc d, LayoutSel L, const double* in) {
+  using Tr = StorageTraits<S>;
+  const int64_t N = int64_t(d.nx) * d.ny;
+  const int64_t n = int64_t(blockIdx.x) * kBlock + threadIdx.x;
+  if (n >= N) return;
+  const int y = int(n / d.nx), x = int(n - int64_t(y) * d.nx);
+  const double th = d.theta;
+#pragma unroll
+  for (int i = 0; i < Q; ++i) {
+    const double w = (cx(i) == 0 ? 1.0 - th : 0.5 * th) * (cy(i) == 0 ? 1.0 - th : 0.5 * th);
+    buf[layout_index(i, x, y, d.nx, d.ny, d.pitch, d.plane, L)] = Tr::store(typename Tr::T(in[i * N + n] - w * d.rho0));
+  }
+}
+
+// rho, j of one node from the stored state, accumulated in FP64.
+template <class S>
+__device__ __forceinline__ void node_moments(const S* buf, const RunDesc& d, LayoutSel L, int x, int y,
+                                             double& drho, double& jx, double& jy, bool* bad = nullptr) {
+  using Tr = StorageTraits<S>;
+  drho = jx = jy = 0.0;
+  bool nf = false;
+#pragma unroll
+  for (int i = 0; i < Q; ++i) {
+    const double g = double(Tr::load(buf[layout_index(i, x, y, d.nx, d.ny, d.pitch, d.plane, L)]));
+    nf |= !isfinite(g);
+    drho += g;
+    jx += cx(i) * g;
+    jy += cy(i) * g;
+  }
+  if (bad) *bad = nf;
+}
+
+template <class S, class O>
+__global__ void __launch_bounds__(kBlock)
+k_moments(const S* buf, RunDesc d, LayoutSel L, O* rho, O* ux, O* uy) {
+  const int64_t n = int64_t(blockIdx.x) * kBlock + threadIdx.x;
+  if (n >= int64_t(d.nx) * d.ny) return;
+  const int y = int(n / d.nx), x = int(n - int64_t(y) * d.nx);
+  double drho, jx, jy;
+  node_moments(buf, d, L, x, y, drho, jx, jy);
+  const double r = d.rho0 + drho;
+  if (rho) rho[n] = O(r);
+  if (ux) ux[n] = O(jx / r);
+  if (uy) uy[n] = O(jy / r);
+}
+
+// FP64 totals, first stage: fixed grid of kReduceBlocks blocks, deterministic order.
+template <class S>
+__global__ void __launch_bounds__(kBlock)
+k_reduce_partial(const S* buf, RunDesc d, LayoutSel L, double* partial) {
+  __shared__ double sh[4][kBlock];
+  const int64_t N = int64_t(d.nx) * d.ny;
+  double s0 = 0, s1 = 0, s2 = 0, s3 = 0;
+  for (int64_t n = int64_t(blockIdx.x) * kBlock + threadIdx.x; n < N; n += int64_t(gridDim.x) * kBlock) {
+    const int y = int(n / d.nx), x = int(n - int64_t(y) * d.nx);
+    double drho, jx, jy;
+    bool bad;
+    node_moments(buf, d, L, x, y, drho, jx, jy, &bad);
+    s0 += drho;
+    s1 += jx;
+    s2 += jy;
+    s3 += bad ? 1.0 : 0.0;
+  }
+  sh[0][threadIdx.x] = s0;
+  sh[1][threadIdx.x] = s1;
+  sh[2][threadIdx.x] = s2;
+  sh[3][threadIdx.x] = s3;
+  __syncthreads();
+  for (int w = kBlock / 2; w > 0; w >>= 1) {
+    if (int(threadIdx.x) < w)
+      for (int c = 0; c < 4; ++c) sh[c][threadIdx.x] += sh[c][threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x < 4) partial[blockIdx.x * 4 + threadIdx.x] = sh[threadIdx.x][0];
+}
+
+// Second stage: one block sums the partials; result = {sum rho, sum jx, sum jy, #non-finite}.
+template <class S>
+__global__ void __launch_bounds__(kBlock)
+k_reduce_final(const double* partial, int nparts, double mass_offset, double* result) {
+  __shared__ double sh[4][kBlock];
+  double s[4] = {0, 0, 0, 0};
+  for (int b = threadIdx.x; b < nparts; b += kBlock)
+    for (int c = 0; c < 4; ++c) s[c] += partial[b * 4 + c];
+  for (int c = 0; c < 4; ++c) sh[c][threadIdx.x] = s[c];
+  __syncthreads();
+  for (int w = kBlock / 2; w > 0; w >>= 1) {
+    if (int(threadIdx.x) < w)
+      for (int c = 0; c < 4; ++c) sh[c][threadIdx.x] += sh[c][threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    result[0] = mass_offset + sh[0][0];
+    result[1] = sh[1][0];
+    result[2] = sh[2][0];
+    result[3] = sh[3][0];
+  }
+}
+
+// Adjoint seed: fbar^N_i = rho_bar + u_bar . (c_i - u)/rho (derivative of rho and
+// u = sum c f / rho with respect to f_i), written to the natural-layout fbar planes.
+template <class S, class T>
+__global__ void __launch_bounds__(kBlock)
+k_seed(const S* buf, RunDesc d, LayoutSel L, const T* rhob, const T* uxb, const T* uyb, T* fbar) {
+  const int64_t n = int64_t(blockIdx.x) * kBlock + threadIdx.x;
+  if (n >= int64_t(d.nx) * d.ny) return;
+  const int y = int(n / d.nx), x = int(n - int64_t(y) * d.nx);
+  double drho, jx, jy;
+  node_moments(buf, d, L, x, y, drho, jx, jy);
+  const T r = T(d.rho0 + drho);
+  const T vx = T(jx / (d.rho0 + drho)), vy = T(jy / (d.rho0 + drho));
+  const T rb = rhob ? rhob[n] : T(0);
+  const T ax = uxb[n] / r, ay = uyb[n] / r;
+#pragma unroll
+  for (int i = 0; i < Q; ++i)
+    fbar[i * d.plane_t + int64_t(y) * d.pitch + x] = rb + ax * (T(cx(i)) - vx) + ay * (T(cy(i)) - vy);
+}
+
+template <class T>
+__global__ void __launch_bounds__(kBlock) k_fbar_import(RunDesc d, const T* dense, T* fbar) {
+  const int64_t N = int64_t(d.nx) * d.ny;
+  const int64_t n = int64_t(blockIdx.x) * kBlock + threadIdx.x;
+  if (n >= N) return;
+  const int y = int(n / d.nx), x = int(n - int64_t(y) * d.nx);
+#pragma unroll
+  for (int i = 0; i < Q; ++i) fbar[i * d.plane_t + int64_t(y) * d.pitch + x] = dense[i * N + n];
+}
+
+template <class T>
+__global__ void __launch_bounds__(kBlock) k_fbar_export(RunDesc d, const T* fbar, T* dense) {
+  const int64_t N = int64_t(d.nx) * d.ny;
+  const int64_t n = int64_t(blockIdx.x) * kBlock + threadIdx.x;
+  if (n >= N) return;
+  const int y = int(n / d.nx), x = int(n - int64_t(y) * d.nx);
+#pragma unroll
+  for (int i = 0; i < Q; ++i) dense[i * N + n] = fbar[i * d.plane_t + int64_t(y) * d.pitch + x];
+}
+
+// Initial-condition adjoint: f^0 = f^eq(rho0_field, u0) with rho held fixed, so
+// u0bar_a = sum_i fbar^0_i d f_i^eq / d u_a, with dPhi(0,u)/du = -2u, dPhi(+-1,u)/du = u +- 1/2.
+// rho and u are the moments of the recorded state at t = 0.
+template <class S, class T>
+__global__ void __launch_bounds__(kBlock)
+k_ic_adjoint(const S* buf0, RunDesc d, LayoutSel L, const T* fbar, T* uxb, T* uyb) {
+  const int64_t n = int64_t(blockIdx.x) * kBlock + threadIdx.x;
+  if (n >= int64_t(d.nx) * d.ny) return;
+  const int y = int(n / d.nx), x = int(n - int64_t(y) * d.nx);
+  double drho, jx, jy;
+  node_moments(buf0, d, L, x, y, drho, jx, jy);
+  const T r = T(d.rho0 + drho);
+  const T vx = T(jx / (d.rho0 + drho)), vy = T(jy / (d.rho0 + drho));
+  const T th = T(d.theta);
+  const T hx[3] = {T(0.5) * (th + vx * vx - vx), T(1) - th - vx * vx, T(0.5) * (th + vx * vx + vx)};
+  const T hy[3] = {T(0.5) * (th + vy * vy - vy), T(1) - th - vy * vy, T(0.5) * (th + vy * vy + vy)};
+  const T gx[3] = {vx - T(0.5), T(-2) * vx, vx + T(0.5)};
+  const T gy[3] = {vy - T(0.5), T(-2) * vy, vy + T(0.5)};
+  T ax = T(0), ay = T(0);
+#pragma unroll
+  for (int i = 0; i < Q; ++i) {
+    const int a = cx(i) + 1, b = cy(i) + 1;
+    const T fb = fbar[i * d.plane_t + int64_t(y) * d.pitch + x];
+    ax += fb * r * gx[a] * hy[b];
+    ay += fb * r * hx[a] * gy[b];
+  }
+  uxb[n] = ax;
+  uyb[n] = ay;
+}
+
+// --- step dispatch ---------------------------------------------------------------------------
+
+template <class S, int VEC, int MODEL>
+hipError_t launch_step_v(const RunDesc& d, int phase, const void* src, void* dst, void* rec, hipStream_t st) {
+  using T = typename StorageTraits<S>::T;
+  const Geo g = make_geo(d, VEC, d.plane);
+  const Coef<T> k = make_coef<T>(d);
+  const S* s = static_cast<const S*>(src);
+  S* o = static_cast<S*>(dst);
+  T* r = static_cast<T*>(rec);
+  const dim3 grid = step_grid(g), block(kBlock);
+  if (rec) {
+    if (phase == PH_AB) hipLaunchKernelGGL((k_step<S, VEC, MODEL, PH_AB, true>), grid, block, 0, st, s, o, g, k, r, d.plane_t);
+    else if (phase == PH_AA_EVEN) hipLaunchKernelGGL((k_step<S, VEC, MODEL, PH_AA_EVEN, true>), grid, block, 0, st, s, o, g, k, r, d.plane_t);
+    else hipLaunchKernelGGL((k_step<S, VEC, MODEL, PH_AA_ODD, true>), grid, block, 0, st, s, o, g, k, r, d.plane_t);
+  } else {
+    if (phase == PH_AB) hipLaunchKernelGGL((k_step<S, VEC, MODEL, PH_AB, false>), grid, block, 0, st, s, o, g, k, r, d.plane_t);
+    else if (phase == PH_AA_EVEN) hipLaunchKernelGGL((k_step<S, VEC, MODEL, PH_AA_EVEN, false>), grid, block, 0, st, s, o, g, k, r, d.plane_t);
+    else hipLaunchKernelGGL((k_step<S, VEC, MODEL, PH_AA_ODD, false>), grid, block, 0, st, s, o, g, k, r, d.plane_t);
+  }
+  return hipGetLastError();
+}
+
+template <class S, int VEC>
+hipError_t launch_step_m(const RunDesc& d, int phase, const void* src, void* dst, void* rec, hipStream_t st) {
+  switch (d.model) {
+    case M_BGK: return launch_step_v<S, VEC, M_BGK>(d, phase, src, dst, rec, st);
+    case M_UC: return launch_step_v<S, VEC, M_UC>(d, phase, src, dst, rec, st);
+    case M_PARTIAL: return launch_step_v<S, VEC, M_PARTIAL>(d, phase, src, dst, rec, st);
+    default: return launch_step_v<S, VEC, M_COMPLETE>(d, phase, src, dst, rec, st);
+  }
+}
+
+// Nodes per thread: 16 bytes of each population per thread (default), or the narrower
+// variants kept for tuning sweeps.
+template <class S>
+struct VecChoice;
+template <> struct VecChoice<double> { static constexpr int a = 2, b = 1, c = 1; };
+template <> struct VecChoice<float> { static constexpr int a = 4, b = 2, c = 1; };
+template <> struct VecChoice<_Float16> { static constexpr int a = 8, b = 4, c = 2; };
+template <> struct VecChoice<bf16_t> { static constexpr int a = 8, b = 4, c = 2; };
+
+template <class S>
+hipError_t Engine<S>::step(const RunDesc& d, int phase, const void* src, void* dst, void* rec, hipStream_t st) {
+  using V = VecChoice<S>;
+  if (d.vec == V::a) return launch_step_m<S, V::a>(d, phase, src, dst, rec, st);
+  if (d.vec == V::b) return launch_step_m<S, V::b>(d, phase, src, dst, rec, st);
+  if (d.vec == V::c) return launch_step_m<S, V::c>(d, phase, src, dst, rec, st);
+  return hipErrorInvalidValue;
+}
+
+template <class S>
+hipError_t Engine<S>::init(const RunDesc& d, LayoutSel L, void* buf, const double* rho, const double* ux,
+                           const double* uy, hipStream_t st) {
+  hipLaunchKernelGGL(k_init<S>, dim3(node_blocks(d)), dim3(kBlock), 0, st, static_cast<S*>(buf), d, L, rho, ux, uy);
+  return hipGetLastError();
+}
+
+template <class S>
+hipError_t Engine<S>::get(const RunDesc& d, LayoutSel L, const void* buf, bool out_f64, void* out, hipStream_t st) {
+  if (out_f64)
+    hipLaunchKernelGGL((k_get<S, double>), dim3(node_blocks(d)), dim3(kBlock), 0, st, static_cast<const S*>(buf), d, L,
+                       static_cast<double*>(out));
+  else
+    hipLaunchKernelGGL((k_get<S, float>), dim3(node_blocks(d)), dim3(kBlock), 0, st, static_cast<const S*>(buf), d, L,
+                       static_cast<float*>(out));
+  return hipGetLastError();
+}
+
+template <class S>
+hipError_t Engine<S>::set(const RunDesc& d, LayoutSel L, void* buf, const double* in, hipStream_t st) {
+  hipLaunchKernelGGL(k_set<S>, dim3(node_blocks(d)), dim3(kBlock), 0, st, static_cast<S*>(buf), d, L, in);
+  return hipGetLastError();
+}
+
+template <class S>
+hipError_t Engine<S>::moments(const RunDesc& d, LayoutSel L, const void* buf, bool out_f64, void* rho, void* ux,
+                              void* uy, hipStream_t st) {
+  if (out_f64)
+    hipLaunchKernelGGL((k_moments<S, double>), dim3(node_blocks(d)), dim3(kBlock), 0, st, static_cast<const S*>(buf), d,
+                       L, static_cast<double*>(rho), static_cast<double*>(ux), static_cast<double*>(uy));
+  else
+    hipLaunchKernelGGL((k_moments<S, float>), dim3(node_blocks(d)), dim3(kBlock), 0, st, static_cast<const S*>(buf), d,
+                       L, static_cast<float*>(rho), static_cast<float*>(ux), static_cast<float*>(uy));
+  return hipGetLastError();
+}
+
+template <class S>
+hipError_t Engine<S>::invariants(const RunDesc& d, LayoutSel L, const void* buf, double* partial, double* result,
+                                 hipStream_t st) {
+  hipLaunchKernelGGL(k_reduce_partial<S>, dim3(kReduceBlocks), dim3(kBlock), 0, st, static_cast<const S*>(buf), d, L,
+                     partial);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_reduce_final<S>, dim3(1), dim3(kBlock), 0, st, partial, kReduceBlocks,
+                     d.rho0 * double(d.nx) * double(d.ny), result);
+  return hipGetLastError();
+}
+
+template <class S>
+hipError_t Engine<S>::seed(const RunDesc& d, LayoutSel L, const void* buf, const T* rhob, const T* uxb, const T* uyb,
+                           T* fbar, hipStream_t st) {
+  hipLaunchKernelGGL((k_seed<S, T>), dim3(node_blocks(d)), dim3(kBlock), 0, st, static_cast<const S*>(buf), d, L, rhob,
+                     uxb, uyb, fbar);
+  return hipGetLastError();
+}
+
+template <class S>
+hipError_t Engine<S>::fbar_import(const RunDesc& d, const T* dense, T* fbar, hipStream_t st) {
+  hipLaunchKernelGGL(k_fbar_import<T>, dim3(node_blocks(d)), dim3(kBlock), 0, st, d, dense, fbar);
+  return hipGetLastError();
+}
+
+template <class S>
+hipError_t Engine<S>::fbar_export(const RunDesc& d, const T* fbar, T* dense, hipStream_t st) {
+  hipLaunchKernelGGL(k_fbar_export<T>, dim3(node_blocks(d)), dim3(kBlock), 0, st, d, fbar, dense);
+  return hipGetLastError();
+}
+
+template <class S>
+hipError_t Engine<S>::adjoint_step(const RunDesc& d, const T* fbar_next, T* fbar, const T* rec, hipStream_t st) {
+  constexpr int V = 16 / int(sizeof(T));
+  const Geo g = make_geo(d, V, d.plane_t);
+  const Coef<T> k = make_coef<T>(d);
+  const dim3 grid = step_grid(g), block(kBlock);
+  switch (d.model) {
+    case M_BGK: hipLaunchKernelGGL((k_adjoint_step<T, V, M_BGK>), grid, block, 0, st, fbar_next, fbar, g, k, rec, d.plane_t); break;
+    case M_UC: hipLaunchKernelGGL((k_adjoint_step<T, V, M_UC>), grid, block, 0, st, fbar_next, fbar, g, k, rec, d.plane_t); break;
+    case M_PARTIAL: hipLaunchKernelGGL((k_adjoint_step<T, V, M_PARTIAL>), grid, block, 0, st, fbar_next, fbar, g, k, rec, d.plane_t); break;
+    default: hipLaunchKernelGGL((k_adjoint_step<T, V, M_COMPLETE>), grid, block, 0, st, fbar_next, fbar, g, k, rec, d.plane_t); break;
+  }
+  return hipGetLastError();
+}
+
+template <class S>
+hipError_t Engine<S>::ic_adjoint(const RunDesc& d, LayoutSel L, const void* buf0, const T* fbar, T* uxb, T* uyb,
+                                 hipStream_t st) {
+  hipLaunchKernelGGL((k_ic_adjoint<S, T>), dim3(node_blocks(d)), dim3(kBlock), 0, st, static_cast<const S*>(buf0), d, L,
+                     fbar, uxb, uyb);
+  return hipGetLastError();
+}
+
+}  // namespace lbm

@@ -1,0 +1,146 @@
+"""Parity of the HIP forward path (through the C ABI) with the FP64 oracle.
+
+Tolerances on eps_f = max|f - f_ref| / max|f_ref|: 1e-12 for FP64 storage, 1e-5 for FP32,
+1e-3 for FP16 storage; BF16 storage is reported with a looser bound (8 significant bits).
+"""
+import numpy as np
+import pytest
+
+import lbm_inputs as inp
+import oracle
+from tests.gpu_util import gather_nodes, gpu_sim, oracle_light_cone, sample_nodes
+from tests.lbm_diag import eps_f
+
+pytestmark = pytest.mark.gpu
+
+MODELS = ["bgk", "uc", "partial", "complete"]
+TOL = {"f64": 1e-12, "f32": 1e-5, "f16": 1e-3, "bf16": 1e-2}
+# Tiny grids: several thread groups, ragged row tails (nx not a multiple of the vector
+# width), single-node and single-row/column boxes where streaming wraps onto itself.
+GRIDS = [(8, 4), (16, 3), (13, 5), (1, 1), (1, 7), (7, 1), (37, 9), (2, 2), (5, 64)]
+
+
+@pytest.mark.parametrize("storage", ["f64", "f32", "f16", "bf16"])
+@pytest.mark.parametrize("pattern", ["ab", "aa"])
+def test_init_is_guided_equilibrium(storage, pattern):
+    nx, ny, th = 37, 11, 0.4
+    fields = inp.random_fields(nx, ny, seed=11, rho_spread=0.05, u_max=0.15)
+    sim = gpu_sim(nx, ny, th, 0.02, "complete", storage, pattern, fields=fields)
+    got = sim.populations().cpu().numpy()
+    ref = oracle.init_equilibrium(*fields, th)
+    tol = {"f64": 1e-15, "f32": 2e-8, "f16": 1e-4, "bf16": 1e-3}[storage]
+    assert eps_f(got, ref) <= tol
+    rho, ux, uy = (a.cpu().numpy() for a in sim.moments())
+    np.testing.assert_allclose(rho, fields[0], rtol=0, atol=50 * tol)
+    np.testing.assert_allclose(ux, fields[1], rtol=0, atol=50 * tol)
+
+
+@pytest.mark.parametrize("pattern", ["ab", "aa"])
+@pytest.mark.parametrize("model", MODELS)
+def test_few_steps_on_random_populations_fp64(model, pattern):
+    """Arbitrary (non-equilibrium) populations, 1-3 steps: exercises both AA phases."""
+    th, nu = 0.4, 0.02
+    for (nx, ny) in GRIDS:
+        f0 = inp.random_populations(nx, ny, seed=31 * nx + ny)
+        for n in (1, 2, 3):
+            sim = gpu_sim(nx, ny, th, nu, model, "f64", pattern, f0=f0)
+            sim.step(n)
+            e = eps_f(sim.populations().cpu().numpy(), oracle.run(f0, th, nu, model, n))
+            assert e <= 1e-13, (nx, ny, n, e)
+
+
+@pytest.mark.parametrize("pattern", ["ab", "aa"])
+@pytest.mark.parametrize("model", MODELS)
+def test_taylor_green_64_fp64_1000_steps(model, pattern):
+    """Taylor-Green 64^2, theta = 1/3, nu = 0.01, U0 = 0.05 (+ noise 1e-3), 1000 steps, FP64."""
+    w = inp.WORKLOADS["tg64"]
+    fields = inp.taylor_green(64, 64, 0.05, w.theta, noise=1e-3, seed=0)
+    sim = gpu_sim(64, 64, w.theta, w.nu, model, "f64", pattern, fields=fields)
+    inv0 = np.array(sim.invariants())
+    sim.step(1000)
+    ref = oracle.run(oracle.init_equilibrium(*fields, w.theta), w.theta, w.nu, model, 1000)
+    assert eps_f(sim.populations().cpu().numpy(), ref) <= 1e-12
+    inv1 = np.array(sim.invariants())
+    assert abs(inv1[0] - inv0[0]) / inv0[0] < 1e-13
+    if model != "uc":
+        assert np.max(np.abs(inv1[1:] - inv0[1:])) < 1e-11
+
+
+@pytest.mark.parametrize("model,steps", [("complete", 2000), ("bgk", 2000), ("partial", 40)])
+@pytest.mark.parametrize("pattern", ["ab", "aa"])
+def test_taylor_green_theta03_fp32(model, steps, pattern):
+    """The FP32 workload (theta = 0.3, nu = 0.005, U0 = 0.1, noise 1e-3) on a 256^2 box for
+    its full 2000 steps; the partial model is linearly unstable there and is compared over
+    the window before its blow-up."""
+    n, th, nu = 256, 0.3, 0.005
+    fields = inp.taylor_green(n, n, 0.1, th, noise=1e-3, seed=0)
+    sim = gpu_sim(n, n, th, nu, model, "f32", pattern, fields=fields)
+    sim.step(steps)
+    ref = oracle.run(oracle.init_equilibrium(*fields, th), th, nu, model, steps)
+    e = eps_f(sim.populations().cpu().numpy(), ref)
+    print(f"eps_f {model} {pattern} {steps} steps: {e:.3e}")
+    assert e <= TOL["f32"]
+
+
+@pytest.mark.parametrize("storage", ["f16", "bf16"])
+@pytest.mark.parametrize("model", ["complete", "bgk"])
+def test_reduced_precision_storage(storage, model):
+    """Shifted 16-bit storage with FP32 arithmetic on Taylor-Green 64^2, 1000 steps."""
+    w = inp.WORKLOADS["tg64"]
+    fields = inp.taylor_green(64, 64, 0.05, w.theta, noise=1e-3, seed=0)
+    sim = gpu_sim(64, 64, w.theta, w.nu, model, storage, "ab", fields=fields)
+    sim.step(1000)
+    ref = oracle.run(oracle.init_equilibrium(*fields, w.theta), w.theta, w.nu, model, 1000)
+    e = eps_f(sim.populations().cpu().numpy(), ref)
+    print(f"eps_f {storage} {model}: {e:.3e}")
+    assert e <= TOL[storage]
+
+
+FULL = [
+    ("tg4096", "complete", "f32", "ab"), ("tg4096", "bgk", "f32", "ab"), ("tg4096", "partial", "f32", "ab"),
+    ("tg4096", "complete", "f32", "aa"), ("turb8192", "complete", "f16", "aa"), ("turb8192", "complete", "bf16", "ab"),
+    ("turb8192", "complete", "f64", "ab"), ("dsl16384", "complete", "f32", "aa"),
+]
+
+
+@pytest.mark.parametrize("name,model,storage,pattern", FULL)
+def test_full_size_sampled_nodes(name, model, storage, pattern):
+    """At the workloads' full sizes, in the launch configuration the benchmark times: the
+    populations of sampled nodes after k steps against the oracle run on each node's
+    light cone (a periodic patch of (2k+3)^2 nodes)."""
+    w = inp.WORKLOADS[name]
+    fields = w.fields(seed=0)
+    k = 9 if pattern == "aa" else 8
+    sim = gpu_sim(w.nx, w.ny, w.theta, w.nu, model, storage, pattern, fields=fields)
+    sim.step(k)
+    nodes = sample_nodes(w.nx, w.ny, 24, seed=1)
+    got = gather_nodes(sim.populations(), nodes)
+    ref = oracle_light_cone(fields, w.theta, w.nu, model, k, nodes)
+    scale = max(np.max(np.abs(v)) for v in ref.values())
+    err = max(np.max(np.abs(got[p] - ref[p])) for p in nodes) / scale
+    assert err <= TOL[storage], err
+
+
+def test_nonfinite_population_is_reported():
+    from paper_2602_21242_amd import LBMError, capi
+    f0 = inp.random_populations(9, 6, seed=2)
+    f0[3, 2, 4] = np.nan
+    sim = gpu_sim(9, 6, 0.4, 0.02, "complete", "f32", f0=f0)
+    with pytest.raises(LBMError) as ei:
+        sim.invariants()
+    assert ei.value.status == capi.LBM_ERR_NONFINITE
+
+
+def test_moments_of_populations():
+    nx, ny = 21, 10
+    f0 = inp.random_populations(nx, ny, seed=5)
+    for pattern in ("ab", "aa"):
+        sim = gpu_sim(nx, ny, 0.4, 0.02, "complete", "f64", pattern, f0=f0)
+        sim.step(3)
+        f = sim.populations().cpu().numpy()
+        rho, ux, uy = (a.cpu().numpy() for a in sim.moments())
+        ro, uxo, uyo = oracle.moments(f)
+        np.testing.assert_allclose(rho, ro, rtol=1e-15)
+        np.testing.assert_allclose(ux, uxo, rtol=0, atol=1e-15)
+        np.testing.assert_allclose(uy, uyo, rtol=0, atol=1e-15)
+        assert sim.time == 3
