@@ -1,0 +1,285 @@
+"""Benchmark of the D2Q9 OReg-GEq lattice Boltzmann step on one MI355X.
+
+Headline: GLUPS (10^9 lattice-node updates per second) of the FP32 completely corrected
+OReg-GEq step on the 4096^2 Taylor-Green workload (theta = 0.3, nu = 0.005, U0 = 0.1 plus
+Gaussian velocity noise 1e-3), with the fraction of the HBM roofline at 72 algorithmic
+bytes per node update. Beside it: LBGK and partial models, the AA pattern, FP16/BF16/FP64
+storage on the 8192^2 turbulence workload (with the error against the FP64 run), the
+adjoint step and the end-to-end gradient, a device-to-device copy, and the FP64 CPU oracle
+timed on the host cores.
+
+Prints one JSON line on stdout; progress goes to stderr.
+"""
+import argparse
+import glob
+import hashlib
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0          # MI355X HBM3E peak (vendor figure)
+ALG_BYTES = {"f64": 144, "f32": 72, "f16": 36, "bf16": 36}   # one read + one write of 9 populations
+ADJ_BYTES = {"f64": 184, "f32": 92, "f16": 92, "bf16": 92}   # fbar read + write, 5 recorded moments
+METRIC = "GLUPS & %HBM peak, D2Q9 OReg-GEq step FP32 vs FP16-store; adjoint GLUPS"
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def kernel_source_hash():
+    h = hashlib.sha256()
+    for p in sorted(glob.glob(os.path.join(ROOT, "paper_2602_21242_amd", "csrc", "*"))):
+        with open(p, "rb") as fh:
+            h.update(os.path.basename(p).encode())
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def load_traffic(workload, model, storage, pattern):
+    """HBM bytes per launch from the committed rocprofv3 counter summary, if it was taken
+    on the current kernel sources (else None)."""
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as fh:
+        data = json.load(fh)
+    if data.get("kernel_source_hash") != kernel_source_hash():
+        return None
+    key = f"{workload}/{model}/{storage}/{pattern}"
+    ent = data.get("entries", {}).get(key)
+    return None if ent is None else ent.get("hbm_bytes_per_launch")
+
+
+def make_sim(w, model, storage, pattern, fields, **kw):
+    import torch
+    from paper_2602_21242_amd import Simulation
+    t = lambda a: None if a is None else torch.as_tensor(a, dtype=torch.float64, device="cuda")
+    rho, ux, uy = fields
+    return Simulation(w.nx, w.ny, w.theta, w.nu, t(ux), t(uy), rho=t(rho), model=model, storage=storage,
+                      pattern=pattern, **kw)
+
+
+def time_steps(sim, steps, warmup):
+    """Average milliseconds per step over `steps` steps after `warmup` untimed ones, HIP events
+    recorded on the stream the library launches on."""
+    import torch
+    sim.step(warmup)
+    torch.cuda.synchronize()
+    start = torch.cuda.Event(enable_timing=True)
+    stop = torch.cuda.Event(enable_timing=True)
+    start.record(sim.stream)
+    sim.step(steps)
+    stop.record(sim.stream)
+    torch.cuda.synchronize()
+    return start.elapsed_time(stop) / steps
+
+
+def copy_bandwidth(nbytes=2 << 30, reps=20):
+    import torch
+    a = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
+    b = torch.empty_like(a)
+    b.copy_(a)
+    torch.cuda.synchronize()
+    s, e = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    s.record()
+    for _ in range(reps):
+        b.copy_(a)
+    e.record()
+    torch.cuda.synchronize()
+    ms = s.elapsed_time(e) / reps
+    del a, b
+    return 2 * nbytes / (ms * 1e-3) / 1e9
+
+
+def cpu_baseline(w, model, budget_s=15.0):
+    """The FP64 CPU oracle on the same workload (full grid), timed for a bounded number of
+    steps on the host cores."""
+    import oracle
+    rho, ux, uy = w.fields(seed=0)
+    f = oracle.init_equilibrium(rho, ux, uy, w.theta)
+    t0 = time.perf_counter()
+    f = oracle.run(f, w.theta, w.nu, model, 1)
+    one = time.perf_counter() - t0
+    n = max(1, min(50, int(budget_s / max(one, 1e-6))))
+    t0 = time.perf_counter()
+    oracle.run(f, w.theta, w.nu, model, n)
+    dt = time.perf_counter() - t0
+    glups = w.nx * w.ny * n / dt / 1e9
+    return {"value": glups, "unit": "GLUPS", "cores": oracle.num_threads(), "kind": "oracle",
+            "sample": f"{w.name} {w.nx}x{w.ny} {model} model, {n} steps after 1 warm-up step, "
+                      f"{dt:.1f} s, host cpu_count={os.cpu_count()}"}
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=2000)
+    ap.add_argument("--warmup", type=int, default=50)
+    ap.add_argument("--workload", default="tg4096")
+    ap.add_argument("--model", default="complete")
+    ap.add_argument("--storage", default="f32")
+    ap.add_argument("--pattern", default="aa")
+    ap.add_argument("--quick", action="store_true", help="headline only: no variants, no CPU baseline")
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--precision-steps", type=int, default=1000,
+                    help="steps of the 8192^2 storage-precision comparison")
+    ap.add_argument("--copy-probe", type=int, default=0,
+                    help="only run a device-to-device copy of this many bytes (counter scaling)")
+    args = ap.parse_args()
+
+    if args.gpus != 1:
+        print(f"bench.py: this build runs on one GPU only (asked for --gpus {args.gpus}); the multi-GPU "
+              f"slab decomposition is a design, not a built path", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import lbm_inputs as inp
+    if not torch.cuda.is_available():
+        print("bench.py: no GPU visible", file=sys.stderr)
+        sys.exit(1)
+    torch.cuda.set_device(0)
+
+    if args.copy_probe:
+        a = torch.ones(args.copy_probe, dtype=torch.uint8, device="cuda")
+        b = torch.empty_like(a)
+        for _ in range(3):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        log(f"copy probe: 3 x {args.copy_probe} bytes")
+        return
+
+    w = inp.WORKLOADS[args.workload]
+    nodes = w.nx * w.ny
+    log(f"[bench] headline: {w.name} {w.nx}x{w.ny} {args.model} {args.storage} {args.pattern}, "
+        f"{args.warmup} warm-up + {args.steps} timed steps")
+    fields = w.fields(seed=0)
+    sim = make_sim(w, args.model, args.storage, args.pattern, fields)
+    ms = time_steps(sim, args.steps, args.warmup)
+    inv = sim.invariants(allow_nonfinite=True)
+    del sim
+    glups = nodes / (ms * 1e-3) / 1e9
+    achieved = ALG_BYTES[args.storage] * nodes / (ms * 1e-3) / 1e9
+    log(f"[bench] {ms:.4f} ms/step, {glups:.2f} GLUPS, {achieved:.0f} GB/s algorithmic")
+    traffic = load_traffic(w.name, args.model, args.storage, args.pattern)
+
+    out = {
+        "metric": METRIC, "value": glups, "unit": "GLUPS", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": ms, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f32" if args.storage != "f64" else "f64", "data": "synthetic",
+        "config": {"workload": w.name, "nx": w.nx, "ny": w.ny, "theta": w.theta, "nu": w.nu,
+                   "model": args.model, "storage": args.storage, "pattern": args.pattern,
+                   "initial_field": "Taylor-Green U0=0.1 + N(0,1e-3^2) velocity noise, seed 0"
+                   if w.name == "tg4096" else w.extra},
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
+                     "kernel": f"k_step<{args.storage},{args.model},{args.pattern}>",
+                     "alg_bytes_per_node": ALG_BYTES[args.storage]},
+        "mass_after_run": inv[0] if inv else None,
+    }
+
+    if not args.quick:
+        var = {}
+        log("[bench] copy bandwidth")
+        var["d2d_copy_GBs"] = copy_bandwidth()
+        steps_v = max(100, min(args.steps, 500))
+        for model, pattern in (("complete", "ab"), ("complete", "aa"), ("bgk", "ab"), ("bgk", "aa"),
+                               ("uc", "aa"), ("partial", "aa")):
+            log(f"[bench] variant tg4096 {model} f32 {pattern}")
+            s = make_sim(w, model, "f32", pattern, fields)
+            m = time_steps(s, steps_v, 20)
+            var[f"tg4096/{model}/f32/{pattern}"] = {"ms_per_step": m, "GLUPS": nodes / (m * 1e-3) / 1e9,
+                                                    "hbm_frac": 72 * nodes / (m * 1e-3) / 1e9 / HBM_PEAK_GBS}
+            del s
+        del fields
+        # Storage types on the 8192^2 turbulence workload, with the error against the FP64 run.
+        wt = inp.WORKLOADS["turb8192"]
+        log("[bench] generating turb8192 fields")
+        tf = wt.fields(seed=0)
+        nt = wt.nx * wt.ny
+        ref = None
+        for storage in ("f64", "f32", "f16", "bf16"):
+            log(f"[bench] variant turb8192 complete {storage} aa")
+            s = make_sim(wt, "complete", storage, "aa", tf)
+            m = time_steps(s, 200, 20)
+            ent = {"ms_per_step": m, "GLUPS": nt / (m * 1e-3) / 1e9,
+                   "hbm_frac": ALG_BYTES[storage] * nt / (m * 1e-3) / 1e9 / HBM_PEAK_GBS}
+            del s
+            if args.precision_steps > 0:
+                s = make_sim(wt, "complete", storage, "aa", tf)
+                s.step(args.precision_steps)
+                f = s.populations(dtype=torch.float64)
+                if storage == "f64":
+                    ref = f
+                    fmax = ref.abs().max().item()
+                else:
+                    ent[f"eps_f_vs_f64_after_{args.precision_steps}"] = (f - ref).abs().max().item() / fmax
+                del s, f
+            var[f"turb8192/complete/{storage}/aa"] = ent
+        del ref, tf
+        # Adjoint: the adjoint step kernel at 4096^2 (HBM-bound) and the end-to-end gradient on
+        # the 1024^2 advected shear wave (500 steps, sqrt(N) checkpoints).
+        log("[bench] adjoint")
+        var.update(bench_adjoint(inp))
+        out["variants"] = var
+        if not args.no_cpu:
+            log("[bench] CPU oracle baseline")
+            out["cpu_baseline"] = cpu_baseline(w, args.model)
+    out["kernel_source_hash"] = kernel_source_hash()
+    print(json.dumps(out), flush=True)
+
+
+def bench_adjoint(inp):
+    import torch
+    res = {}
+    # Adjoint step kernel alone: time the reverse sweep of a recorded run and subtract the
+    # recomputation (a forward step with moment recording per adjoint step).
+    w = inp.WORKLOADS["tg4096"]
+    fields = w.fields(seed=0)
+    N = 64
+    sim = make_sim(w, "complete", "f32", "aa", fields, record_steps=N, ckpt_stride=8)
+    sim.step(N)
+    z = torch.zeros((w.ny, w.nx), dtype=torch.float32, device="cuda")
+    sim.adjoint(None, z + 1e-3, z)  # warm-up
+    torch.cuda.synchronize()
+    s, e = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    s.record(sim.stream)
+    sim.adjoint(None, z + 1e-3, z)
+    e.record(sim.stream)
+    torch.cuda.synchronize()
+    ms_sweep = s.elapsed_time(e)
+    nodes = w.nx * w.ny
+    res["adjoint/tg4096/complete/f32/sweep"] = {
+        "steps": N, "ms_total": ms_sweep, "GLUPS_gradient_sweep": nodes * N / (ms_sweep * 1e-3) / 1e9,
+        "note": "reverse sweep = checkpoint restore + recorded recomputation + adjoint step per step"}
+    del sim
+    # End-to-end gradient of the final kinetic energy on the 1024^2 shear wave.
+    from paper_2602_21242_amd import LBMFunction
+    wa = inp.WORKLOADS["shear1024"]
+    rho, ux, uy = wa.fields(seed=0)
+    cfg = dict(nx=wa.nx, ny=wa.ny, theta=wa.theta, nu=wa.nu, steps=wa.steps, model="complete", storage="f32",
+               pattern="aa")
+    t = lambda a: torch.as_tensor(a, dtype=torch.float32, device="cuda")
+    for rep in range(2):
+        ux0 = t(ux).requires_grad_(True)
+        uy0 = t(uy).requires_grad_(True)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        r, vx, vy = LBMFunction.apply(ux0, uy0, cfg)
+        E = 0.5 * (r * (vx * vx + vy * vy)).sum()
+        E.backward()
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+    res["gradient/shear1024/complete/f32/aa"] = {
+        "steps": wa.steps, "s_total": dt, "GLUPS_end_to_end": wa.nx * wa.ny * wa.steps / dt / 1e9,
+        "note": "forward with checkpoints + recomputation + adjoint, cache-resident size"}
+    return res
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,184 @@
+"""Parity of the HIP discrete adjoint (hand-derived vector-Jacobian product of the collision,
+reverse streaming, sqrt(N) checkpointing with recomputation) with the oracle's
+complex-step adjoint, and of the FP32 gradient with FP64 central finite differences."""
+import numpy as np
+import pytest
+
+import lbm_inputs as inp
+import oracle
+from tests.gpu_util import gpu_sim
+
+pytestmark = pytest.mark.gpu
+
+MODELS = ["bgk", "uc", "partial", "complete"]
+
+
+def _t(a, dtype=None):
+    import torch
+    return torch.as_tensor(a, dtype=dtype or torch.float64, device="cuda")
+
+
+def _oracle_population_adjoint(f0, w, theta, nu, model, n):
+    states = [f0]
+    for _ in range(n - 1):
+        states.append(oracle.run(states[-1], theta, nu, model, 1))
+    fb = w
+    for s in reversed(states):
+        fb = oracle.adjoint_step(s, fb, theta, nu, model)
+    return fb
+
+
+@pytest.mark.parametrize("pattern", ["ab", "aa"])
+@pytest.mark.parametrize("model", MODELS)
+def test_population_adjoint_fp64(model, pattern):
+    """dJ/df^0 from dJ/df^N through N = 7 steps, for several checkpoint spacings (including
+    spacings that do not divide N, one step per segment, and a single segment)."""
+    nx, ny, th, nu, N = 13, 7, 0.4, 0.02, 7
+    f0 = inp.random_populations(nx, ny, seed=21, amp=0.1)
+    w = inp.random_direction((9, ny, nx), seed=22)
+    ref = _oracle_population_adjoint(f0, w, th, nu, model, N)
+    for stride in (0, 1, 2, 3, 7, 10):
+        sim = gpu_sim(nx, ny, th, nu, model, "f64", pattern, f0=f0, record_steps=N, ckpt_stride=stride)
+        sim.step(N)
+        got = sim.adjoint_populations(_t(w)).cpu().numpy()
+        err = np.max(np.abs(got - ref)) / np.max(np.abs(ref))
+        assert err <= 1e-12, (stride, err)
+
+
+@pytest.mark.parametrize("model", MODELS)
+def test_velocity_gradient_fp64_matches_oracle(model):
+    """Gradient of the final kinetic energy E = 1/2 sum rho |u|^2 with respect to the initial
+    velocity (rho fixed), through lbm_adjoint, against the oracle's complex-step gradient."""
+    nx, ny, th, nu, N = 12, 10, 0.4, 0.02, 9
+    rho0, ux0, uy0 = inp.shear_wave(nx, ny, 0.05, (0.1, 0.0), noise=1e-2, seed=3)
+    rN, uxN, uyN = oracle.forward_fields(rho0, ux0, uy0, th, nu, model, N)
+    gx_ref, gy_ref = oracle.gradient(rho0, ux0, uy0, 0.5 * (uxN ** 2 + uyN ** 2), rN * uxN, rN * uyN, th, nu, model, N)
+    for pattern in ("ab", "aa"):
+        sim = gpu_sim(nx, ny, th, nu, model, "f64", pattern, fields=(rho0, ux0, uy0), record_steps=N)
+        sim.step(N)
+        r, vx, vy = sim.moments()
+        gx, gy = sim.adjoint(0.5 * (vx * vx + vy * vy), r * vx, r * vy)
+        scale = max(np.max(np.abs(gx_ref)), np.max(np.abs(gy_ref)))
+        assert np.max(np.abs(gx.cpu().numpy() - gx_ref)) <= 1e-12 * scale
+        assert np.max(np.abs(gy.cpu().numpy() - gy_ref)) <= 1e-12 * scale
+
+
+@pytest.mark.parametrize("storage,tol", [("f32", 1e-5), ("f16", 3e-3)])
+def test_population_adjoint_reduced_precision(storage, tol):
+    nx, ny, th, nu, N = 24, 16, 0.4, 0.02, 6
+    f0 = oracle.init_equilibrium(*inp.random_fields(nx, ny, seed=4, u_max=0.1), th)
+    w = inp.random_direction((9, ny, nx), seed=5)
+    ref = _oracle_population_adjoint(f0, w, th, nu, "complete", N)
+    sim = gpu_sim(nx, ny, th, nu, "complete", storage, "aa", f0=f0, record_steps=N)
+    sim.step(N)
+    got = sim.adjoint_populations(_t(w)).cpu().numpy()
+    assert np.max(np.abs(got - ref)) / np.max(np.abs(ref)) <= tol
+
+
+def _ke(rho, ux, uy):
+    return 0.5 * float((rho * (ux * ux + uy * uy)).sum())
+
+
+def _fd_check(w, model, steps, ndir, pattern="aa", h=1e-5):
+    """FP32 adjoint gradient of the final kinetic energy against FP64 central differences of
+    the GPU FP64 forward (itself pinned to the oracle) along seeded random directions."""
+    import torch
+    rho, ux, uy = w.fields(seed=0)
+    sim = gpu_sim(w.nx, w.ny, w.theta, w.nu, model, "f32", pattern, fields=(rho, ux, uy), record_steps=steps)
+    sim.step(steps)
+    r, vx, vy = sim.moments(dtype=torch.float32)
+    gx, gy = sim.adjoint(0.5 * (vx * vx + vy * vy), r * vx, r * vy)
+    gx, gy = gx.double().cpu().numpy(), gy.double().cpu().numpy()
+
+    def J(dx, dy):
+        s = gpu_sim(w.nx, w.ny, w.theta, w.nu, model, "f64", pattern, fields=(rho, ux + dx, uy + dy))
+        s.step(steps)
+        return _ke(*s.moments())
+
+    errs = []
+    for k in range(ndir):
+        v = inp.random_direction((2, w.ny, w.nx), seed=100 + k)
+        fd = (J(h * v[0], h * v[1]) - J(-h * v[0], -h * v[1])) / (2 * h)
+        ad = float(np.sum(gx * v[0]) + np.sum(gy * v[1]))
+        errs.append(abs(ad - fd) / abs(fd))
+    return errs
+
+
+def test_fp32_gradient_vs_fd_small():
+    w = inp.Workload("shear128", 128, 128, 0.4, 0.01, 100, ("complete",), ("f32",),
+                     extra={"kind": "shear_wave", "A": 0.05, "U": 0.1, "noise": 1e-3})
+    errs = _fd_check(w, "complete", 100, 3)
+    print("relative errors", errs)
+    assert max(errs) <= 1e-4
+
+
+def test_fp32_gradient_vs_fd_full_size():
+    """The 1024^2 advected shear wave, 500 steps, sqrt(N) = 23-step checkpoints."""
+    errs = _fd_check(inp.WORKLOADS["shear1024"], "complete", 500, 2)
+    print("relative errors", errs)
+    assert max(errs) <= 1e-4
+
+
+def test_autograd_function_enstrophy_matches_direct_adjoint():
+    """LBMFunction + a torch objective (enstrophy of the central-difference vorticity) gives
+    the same gradient as finite differences of the FP64 forward."""
+    import torch
+    from paper_2602_21242_amd import LBMFunction
+    nx, ny, th, nu, N = 64, 48, 1 / 3, 2e-3, 40
+    rho, ux, uy = inp.double_shear_layer(nx, ny, 0.1, 20.0, 0.05)
+    cfg = dict(nx=nx, ny=ny, theta=th, nu=nu, steps=N, model="complete", storage="f64", pattern="ab")
+
+    def enstrophy(vx, vy):
+        w = 0.5 * (torch.roll(vy, -1, 1) - torch.roll(vy, 1, 1)) - 0.5 * (torch.roll(vx, -1, 0) - torch.roll(vx, 1, 0))
+        return 0.5 * (w * w).sum()
+
+    uy0 = _t(uy).requires_grad_(True)
+    r, vx, vy = LBMFunction.apply(_t(ux), uy0, cfg)
+    enstrophy(vx, vy).backward()
+    g = uy0.grad.cpu().numpy()
+    v = inp.random_direction((ny, nx), seed=7)
+    h = 1e-5  # FD round-off ~ J eps / h ~ 3e-11 absolute, about 5e-7 of the derivative
+
+    def J(d):
+        _, a, b = LBMFunction.apply(_t(ux), _t(uy + d), cfg)
+        return float(enstrophy(a, b))
+
+    fd = (J(h * v) - J(-h * v)) / (2 * h)
+    assert abs(np.sum(g * v) - fd) <= 1e-5 * abs(fd)
+
+
+def test_adjoint_restores_state_and_repeats():
+    import torch
+    nx, ny, N = 16, 9, 5
+    f0 = inp.random_populations(nx, ny, seed=8)
+    sim = gpu_sim(nx, ny, 0.4, 0.02, "complete", "f32", "aa", f0=f0, record_steps=N, ckpt_stride=2)
+    sim.step(N)
+    before = sim.populations().cpu().numpy()
+    w = _t(inp.random_direction((9, ny, nx), seed=9), torch.float32)
+    a = sim.adjoint_populations(w).cpu().numpy()
+    assert sim.time == N
+    assert np.array_equal(sim.populations().cpu().numpy(), before)
+    b = sim.adjoint_populations(w).cpu().numpy()
+    assert np.array_equal(a, b)
+
+
+def test_adjoint_state_errors():
+    import torch
+    from paper_2602_21242_amd import LBMError, capi
+    nx, ny = 8, 8
+    w = _t(np.zeros((9, ny, nx)), torch.float32)
+    sim = gpu_sim(nx, ny, 0.4, 0.02, "complete", "f32")
+    sim.step(2)
+    with pytest.raises(LBMError) as e:
+        sim.adjoint_populations(w)
+    assert e.value.status == capi.LBM_ERR_STATE
+    sim = gpu_sim(nx, ny, 0.4, 0.02, "complete", "f32", record_steps=3)
+    sim.step(2)
+    with pytest.raises(LBMError) as e:
+        sim.adjoint_populations(w)
+    assert e.value.status == capi.LBM_ERR_STATE
+    sim.step(1)
+    sim.set_populations(np.full((9, ny, nx), 1 / 9))
+    with pytest.raises(LBMError) as e:
+        sim.adjoint_populations(w)
+    assert e.value.status == capi.LBM_ERR_STATE
