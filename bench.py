@@ -124,7 +124,7 @@ def main():
     ap.add_argument("--workload", default="tg4096")
     ap.add_argument("--model", default="complete")
     ap.add_argument("--storage", default="f32")
-    ap.add_argument("--pattern", default="aa")
+    ap.add_argument("--pattern", default="ab")
     ap.add_argument("--quick", action="store_true", help="headline only: no variants, no CPU baseline")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--precision-steps", type=int, default=1000,

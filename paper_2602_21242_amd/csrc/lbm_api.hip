@@ -5,6 +5,7 @@
 
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstdlib>
 #include <cstring>
@@ -37,8 +38,7 @@ size_t storage_size(int dt) { return dt == LBM_F64 ? 8 : dt == LBM_F32 ? 4 : 2; 
 // Workspace regions (byte offsets into the caller's buffer).
 struct Plan {
   size_t esize = 0, tsize = 0;        // storage / compute element sizes
-  size_t plane_bytes = 0, plane_t_bytes = 0;
-  size_t pop_bytes = 0;               // one set of nine planes (storage type)
+  size_t pop_bytes = 0;               // one population set (storage type)
   size_t pop_off[2] = {0, 0};
   size_t red_off = 0, res_off = 0;
   int64_t stride = 0;                 // checkpoint spacing s
@@ -54,7 +54,7 @@ lbm_status validate(const lbm_params* p) {
   if (p->nx < 1 || p->ny < 1) return fail(LBM_ERR_INVALID_ARGUMENT, "nx and ny must be >= 1");
   const int64_t pitch = (int64_t(p->nx) + 7) / 8 * 8;
   if (pitch * int64_t(p->ny) >= (int64_t(1) << 31))
-    return fail(LBM_ERR_INVALID_ARGUMENT, "grid too large: padded plane must hold < 2^31 nodes");
+    return fail(LBM_ERR_INVALID_ARGUMENT, "grid too large: (nx rounded up to 8) * ny must be < 2^31");
   if (!(p->theta > 0.0 && p->theta < 1.0)) return fail(LBM_ERR_INVALID_ARGUMENT, "theta must lie in (0, 1)");
   if (!(p->nu > 0.0) || !std::isfinite(p->nu)) return fail(LBM_ERR_INVALID_ARGUMENT, "nu must be finite and > 0");
   if (!(p->rho0 > 0.0) || !std::isfinite(p->rho0)) return fail(LBM_ERR_INVALID_ARGUMENT, "rho0 must be finite and > 0");
@@ -71,11 +71,9 @@ Plan make_plan(const lbm_params& p) {
   pl.esize = storage_size(p.storage);
   pl.tsize = p.storage == LBM_F64 ? 8 : 4;
   const size_t pitch = (size_t(p.nx) + 7) / 8 * 8;
-  // Planes are 4 KiB multiples plus a 512-byte stagger so that the nine streams of one
-  // step do not start on the same HBM channel.
-  pl.plane_bytes = round_up(pitch * p.ny * pl.esize, 4096) + 512;
-  pl.plane_t_bytes = round_up(pitch * p.ny * pl.tsize, 4096) + 512;
-  pl.pop_bytes = lbm::Q * pl.plane_bytes;
+  // Row-interleaved buffers: ny rows of nine (populations) or five (recorded moments)
+  // population rows of `pitch` elements each, rounded up to 4 KiB.
+  pl.pop_bytes = round_up(size_t(lbm::Q) * pitch * p.ny * pl.esize, 4096);
   size_t off = 0;
   pl.pop_off[0] = off;
   off += pl.pop_bytes;
@@ -94,10 +92,10 @@ Plan make_plan(const lbm_params& p) {
     pl.nck = (N + pl.stride - 1) / pl.stride;
     pl.ckpt_off = off;
     off += size_t(pl.nck + 1) * pl.pop_bytes;
-    pl.rec_slot_bytes = lbm::NREC * pl.plane_t_bytes;
+    pl.rec_slot_bytes = round_up(size_t(lbm::NREC) * pitch * p.ny * pl.tsize, 4096);
     pl.rec_off = off;
     off += size_t(pl.stride) * pl.rec_slot_bytes;
-    pl.fbar_bytes = lbm::Q * pl.plane_t_bytes;
+    pl.fbar_bytes = round_up(size_t(lbm::Q) * pitch * p.ny * pl.tsize, 4096);
     pl.fbar_off[0] = off;
     off += pl.fbar_bytes;
     pl.fbar_off[1] = off;
@@ -243,8 +241,16 @@ lbm_status guarded(F&& f) {
   }
 }
 
-int default_vec(size_t esize) {
-  int v = int(16 / esize);
+// Nodes per thread of the step kernel: the engine's default, or LBM_VEC (tuning sweeps;
+// must name one of the widths the engine instantiates).
+int dispatch_vec(int storage) {
+  int v = 1;
+  switch (storage) {
+    case LBM_F64: v = lbm::Engine<double>::default_vec(); break;
+    case LBM_F32: v = lbm::Engine<float>::default_vec(); break;
+    case LBM_F16: v = lbm::Engine<_Float16>::default_vec(); break;
+    default: v = lbm::Engine<lbm::bf16_t>::default_vec(); break;
+  }
   if (const char* s = std::getenv("LBM_VEC")) {
     const int w = std::atoi(s);
     if (w > 0) v = w;
@@ -291,14 +297,14 @@ lbm_status lbm_init(const lbm_params* p, void* d_workspace, size_t workspace_byt
     d.nx = p->nx;
     d.ny = p->ny;
     d.pitch = int((p->nx + 7) / 8 * 8);
-    d.plane = int64_t(plan.plane_bytes / plan.esize);
-    d.plane_t = int64_t(plan.plane_t_bytes / plan.tsize);
+    d.rs = int64_t(lbm::Q) * d.pitch;
+    d.rs_rec = int64_t(lbm::NREC) * d.pitch;
     d.theta = p->theta;
     d.nu = p->nu;
     d.rho0 = p->rho0;
     d.tau = p->nu / p->theta + 0.5;  // nu = theta (tau - 1/2)
     d.model = p->model;
-    d.vec = default_vec(plan.esize);
+    d.vec = dispatch_vec(p->storage);
     c->time = 0;
     c->cur = 0;
     c->rec_valid = p->record_steps > 0;

@@ -71,6 +71,7 @@ template <class T>
 struct Coef {
   T rho0;
   T omb;          // 1 - 1/tau
+  T omb_inv2th2;  // (1 - 1/tau)/(2 theta^2)
   T r0, r1;       // rest factors 1 - theta, theta/2
   T rr0, rr1;     // rho0 r0, rho0 r1
   T inv2th2;      // 1/(2 theta^2)
@@ -82,6 +83,16 @@ struct Coef {
 // Moments recorded per node and step for the adjoint: rho, u_x, u_y, N_xx, N_xy.
 constexpr int NREC = 5;
 
+// 1/x: FP32 uses the hardware reciprocal refined by one Newton step (within one ulp of the
+// correctly rounded quotient); FP64 divides.
+template <class T>
+__device__ __forceinline__ T recip(T x) { return T(1) / x; }
+template <>
+__device__ __forceinline__ float recip<float>(float x) {
+  const float r = __builtin_amdgcn_rcpf(x);
+  return __builtin_fmaf(r, __builtin_fmaf(-x, r, 1.0f), r);
+}
+
 // ---------------------------------------------------------------------------------------
 // Collision of one node on shifted populations: g -> g* (eq:lbe, first line, with the
 // non-equilibrium part of the chosen model). Optionally returns the recorded moments.
@@ -92,7 +103,7 @@ __device__ __forceinline__ void collide(const T g[Q], T out[Q], const Coef<T>& k
   const T jx = (g[1] - g[3]) + (g[5] - g[6]) + (g[8] - g[7]);
   const T jy = (g[2] - g[4]) + (g[5] - g[7]) + (g[6] - g[8]);
   const T rho = k.rho0 + drho;
-  const T rinv = T(1) / rho;
+  const T rinv = recip(rho);
   const T ux = jx * rinv, uy = jy * rinv;
   const T ux2 = ux * ux, uy2 = uy * uy;
 
@@ -137,7 +148,10 @@ __device__ __forceinline__ void collide(const T g[Q], T out[Q], const Coef<T>& k
     rec[4] = Nxy;
   }
   // f_i^OReg = Phi_x Phi_y [(Cx^2 - Cy^2) N_xx + 2 Cx Cy N_xy] / (2 theta^2), C = c - u (eq:oreg).
-  const T n1 = Nxx * k.inv2th2, n2 = Nxy * (T(2) * k.inv2th2);
+  // Everything downstream (psi, the prefactor, Pi~, Psi) is linear in f^OReg, so the
+  // relaxation factor 1 - 1/tau is folded into N here: fo, psi, pf, Pi~ and Psi below are
+  // all (1 - 1/tau) times the paper's quantities.
+  const T n1 = Nxx * k.omb_inv2th2, n2 = Nxy * (T(2) * k.omb_inv2th2);
   const T Cxm = T(-1) - ux, Cx0 = -ux, Cxp = T(1) - ux;
   const T Cym = T(-1) - uy, Cy0 = -uy, Cyp = T(1) - uy;
   const T X1m = Cxm * Cxm * n1, X10 = Cx0 * Cx0 * n1, X1p = Cxp * Cxp * n1;
@@ -180,8 +194,9 @@ __device__ __forceinline__ void collide(const T g[Q], T out[Q], const Coef<T>& k
       Psi[6] = Psi[8] = s + T(0.25) * Ptxy;
     }
   }
+  // g*_i = (f_i^eq - w_i rho0) + (1 - 1/tau)(f_i^OReg + Psi_i)
 #pragma unroll
-  for (int i = 0; i < Q; ++i) out[i] = feqs[i] + k.omb * (fo[i] + Psi[i]);
+  for (int i = 0; i < Q; ++i) out[i] = feqs[i] + (fo[i] + Psi[i]);
 }
 
 // ---------------------------------------------------------------------------------------
@@ -306,7 +321,7 @@ __device__ __forceinline__ void collide_vjp(const T fbs[Q], const T rec[NREC], c
   rhob += T(-0.5) * Nxxb * (ux2 - uy2) - Nxyb * ux * uy;
   uxb += -Nxxb * rho * ux - Nxyb * rho * uy;
   uyb += Nxxb * rho * uy - Nxyb * rho * ux;
-  const T rinv = T(1) / rho;
+  const T rinv = recip(rho);
   const T jxb = uxb * rinv, jyb = uyb * rinv;
   rhob -= (uxb * ux + uyb * uy) * rinv;
 #pragma unroll

@@ -12,13 +12,14 @@
 namespace lbm {
 
 // Everything a launcher needs to know about a run (host side).
+// Every buffer is row-interleaved: element (i, x, y) at y * row_stride + i * pitch + x.
 struct RunDesc {
-  int nx, ny, pitch;
-  int64_t plane;     // storage-type elements between population planes
-  int64_t plane_t;   // compute-type elements between planes of fbar and of recorded moments
+  int nx, ny, pitch;  // pitch = nx rounded up to 8
+  int64_t rs;         // row stride of the populations and of fbar (9 * pitch)
+  int64_t rs_rec;     // row stride of a recorded-moment slot (5 * pitch)
   double theta, nu, rho0, tau;
   int model;         // M_BGK ... M_COMPLETE
-  int vec;           // nodes per thread of the step and adjoint kernels
+  int vec;           // nodes per thread of the step kernel
 };
 
 // State layout at a given time: f_i(x) = buf[swap ? opp(i) : i][x - shift c_i].
@@ -31,6 +32,7 @@ constexpr int kReduceBlocks = 1024;  // partial sums of the FP64 invariants
 template <class S>
 struct Engine {
   using T = typename StorageTraits<S>::T;
+  static int default_vec();
   static hipError_t step(const RunDesc& d, int phase, const void* src, void* dst, void* rec, hipStream_t st);
   static hipError_t init(const RunDesc& d, LayoutSel L, void* buf, const double* rho, const double* ux,
                          const double* uy, hipStream_t st);
@@ -56,6 +58,7 @@ inline Coef<T> make_coef(const RunDesc& d) {
   const double th = d.theta;
   k.rho0 = T(d.rho0);
   k.omb = T(1.0 - 1.0 / d.tau);
+  k.omb_inv2th2 = T((1.0 - 1.0 / d.tau) / (2.0 * th * th));
   k.r0 = T(1.0 - th);
   k.r1 = T(0.5 * th);
   k.rr0 = T(d.rho0 * (1.0 - th));

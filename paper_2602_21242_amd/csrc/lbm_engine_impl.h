@@ -1,6 +1,8 @@
 // Definitions of Engine<S> (see lbm_engine.h). Included once per storage type.
 #pragma once
 
+#include <algorithm>
+
 #include "lbm_engine.h"
 #include "lbm_step.h"
 
@@ -8,31 +10,30 @@ namespace lbm {
 
 // --- geometry -----------------------------------------------------------------------------
 
-inline Geo make_geo(const RunDesc& d, int vec, int64_t plane) {
+inline Geo make_geo(const RunDesc& d, int vec) {
   Geo g;
   g.nx = d.nx;
   g.ny = d.ny;
-  g.pitch = d.pitch;
-  g.plane = plane;
-  g.ngx = (d.nx + vec - 1) / vec;
-  g.ngroups = g.ngx * d.ny;
-  g.nblocks = (g.ngroups + kBlock - 1) / kBlock;
-  g.nb8 = (g.nblocks + 7) / 8;
+  g.ps = d.pitch;
+  g.rs = d.rs;
+  g.nseg = ((d.nx + vec - 1) / vec + kBlock - 1) / kBlock;
   return g;
 }
 
-inline dim3 step_grid(const Geo& g) { return dim3(unsigned(8 * g.nb8)); }
+inline dim3 step_grid(const Geo& g) {
+  return dim3(unsigned(g.nseg), unsigned(std::min(g.ny, kRowsY)), unsigned((g.ny + kRowsY - 1) / kRowsY));
+}
 
 inline int node_blocks(const RunDesc& d) { return int((int64_t(d.nx) * d.ny + kBlock - 1) / kBlock); }
 
-__device__ __forceinline__ int64_t layout_index(int i, int x, int y, int nx, int ny, int pitch, int64_t plane,
+__device__ __forceinline__ int64_t layout_index(int i, int x, int y, int nx, int ny, int pitch, int64_t rs,
                                                 LayoutSel L) {
   const int slot = L.swap ? opp(i) : i;
   int xs = x - L.shift * cx(i);
   xs = xs < 0 ? xs + nx : (xs >= nx ? xs - nx : xs);
   int ys = y - L.shift * cy(i);
   ys = ys < 0 ? ys + ny : (ys >= ny ? ys - ny : ys);
-  return int64_t(slot) * plane + int64_t(ys) * pitch + xs;
+  return int64_t(ys) * rs + slot * pitch + xs;
 }
 
 // --- per-node auxiliary kernels --------------------------------------------------------------
@@ -58,7 +59,7 @@ k_init(S* buf, RunDesc d, LayoutSel L, const double* rho, const double* ux, cons
     const int a = cx(i) + 1, b = cy(i) + 1;
     const double hx = rr[a] + dx[a], hy = rr[b] + dy[b];
     const double feqs = drho * hx * hy + d.rho0 * (dx[a] * hy + rr[a] * dy[b]);
-    buf[layout_index(i, x, y, d.nx, d.ny, d.pitch, d.plane, L)] = Tr::store(typename Tr::T(feqs));
+    buf[layout_index(i, x, y, d.nx, d.ny, d.pitch, d.rs, L)] = Tr::store(typename Tr::T(feqs));
   }
 }
 
@@ -74,7 +75,7 @@ k_get(const S* buf, RunDesc d, LayoutSel L, O* out) {
 #pragma unroll
   for (int i = 0; i < Q; ++i) {
     const double w = (cx(i) == 0 ? 1.0 - th : 0.5 * th) * (cy(i) == 0 ? 1.0 - th : 0.5 * th);
-    const double g = double(Tr::load(buf[layout_index(i, x, y, d.nx, d.ny, d.pitch, d.plane, L)]));
+    const double g = double(Tr::load(buf[layout_index(i, x, y, d.nx, d.ny, d.pitch, d.rs, L)]));
     out[i * N + n] = O(g + w * d.rho0);
   }
 }
@@ -91,7 +92,7 @@ k_set(S* buf, RunDesc d, LayoutSel L, const double* in) {
 #pragma unroll
   for (int i = 0; i < Q; ++i) {
     const double w = (cx(i) == 0 ? 1.0 - th : 0.5 * th) * (cy(i) == 0 ? 1.0 - th : 0.5 * th);
-    buf[layout_index(i, x, y, d.nx, d.ny, d.pitch, d.plane, L)] = Tr::store(typename Tr::T(in[i * N + n] - w * d.rho0));
+    buf[layout_index(i, x, y, d.nx, d.ny, d.pitch, d.rs, L)] = Tr::store(typename Tr::T(in[i * N + n] - w * d.rho0));
   }
 }
 
@@ -104,7 +105,7 @@ __device__ __forceinline__ void node_moments(const S* buf, const RunDesc& d, Lay
   bool nf = false;
 #pragma unroll
   for (int i = 0; i < Q; ++i) {
-    const double g = double(Tr::load(buf[layout_index(i, x, y, d.nx, d.ny, d.pitch, d.plane, L)]));
+    const double g = double(Tr::load(buf[layout_index(i, x, y, d.nx, d.ny, d.pitch, d.rs, L)]));
     nf |= !isfinite(g);
     drho += g;
     jx += cx(i) * g;
@@ -181,7 +182,7 @@ k_reduce_final(const double* partial, int nparts, double mass_offset, double* re
 }
 
 // Adjoint seed: fbar^N_i = rho_bar + u_bar . (c_i - u)/rho (derivative of rho and
-// u = sum c f / rho with respect to f_i), written to the natural-layout fbar planes.
+// u = sum c f / rho with respect to f_i), written to fbar (population layout, compute type).
 template <class S, class T>
 __global__ void __launch_bounds__(kBlock)
 k_seed(const S* buf, RunDesc d, LayoutSel L, const T* rhob, const T* uxb, const T* uyb, T* fbar) {
@@ -196,7 +197,7 @@ k_seed(const S* buf, RunDesc d, LayoutSel L, const T* rhob, const T* uxb, const 
   const T ax = uxb[n] / r, ay = uyb[n] / r;
 #pragma unroll
   for (int i = 0; i < Q; ++i)
-    fbar[i * d.plane_t + int64_t(y) * d.pitch + x] = rb + ax * (T(cx(i)) - vx) + ay * (T(cy(i)) - vy);
+    fbar[int64_t(y) * d.rs + i * d.pitch + x] = rb + ax * (T(cx(i)) - vx) + ay * (T(cy(i)) - vy);
 }
 
 template <class T>
@@ -206,7 +207,7 @@ __global__ void __launch_bounds__(kBlock) k_fbar_import(RunDesc d, const T* dens
   if (n >= N) return;
   const int y = int(n / d.nx), x = int(n - int64_t(y) * d.nx);
 #pragma unroll
-  for (int i = 0; i < Q; ++i) fbar[i * d.plane_t + int64_t(y) * d.pitch + x] = dense[i * N + n];
+  for (int i = 0; i < Q; ++i) fbar[int64_t(y) * d.rs + i * d.pitch + x] = dense[i * N + n];
 }
 
 template <class T>
@@ -216,7 +217,7 @@ __global__ void __launch_bounds__(kBlock) k_fbar_export(RunDesc d, const T* fbar
   if (n >= N) return;
   const int y = int(n / d.nx), x = int(n - int64_t(y) * d.nx);
 #pragma unroll
-  for (int i = 0; i < Q; ++i) dense[i * N + n] = fbar[i * d.plane_t + int64_t(y) * d.pitch + x];
+  for (int i = 0; i < Q; ++i) dense[i * N + n] = fbar[int64_t(y) * d.rs + i * d.pitch + x];
 }
 
 // Initial-condition adjoint: f^0 = f^eq(rho0_field, u0) with rho held fixed, so
@@ -241,7 +242,7 @@ k_ic_adjoint(const S* buf0, RunDesc d, LayoutSel L, const T* fbar, T* uxb, T* uy
 #pragma unroll
   for (int i = 0; i < Q; ++i) {
     const int a = cx(i) + 1, b = cy(i) + 1;
-    const T fb = fbar[i * d.plane_t + int64_t(y) * d.pitch + x];
+    const T fb = fbar[int64_t(y) * d.rs + i * d.pitch + x];
     ax += fb * r * gx[a] * hy[b];
     ay += fb * r * hx[a] * gy[b];
   }
@@ -254,20 +255,20 @@ k_ic_adjoint(const S* buf0, RunDesc d, LayoutSel L, const T* fbar, T* uxb, T* uy
 template <class S, int VEC, int MODEL>
 hipError_t launch_step_v(const RunDesc& d, int phase, const void* src, void* dst, void* rec, hipStream_t st) {
   using T = typename StorageTraits<S>::T;
-  const Geo g = make_geo(d, VEC, d.plane);
+  const Geo g = make_geo(d, VEC);
   const Coef<T> k = make_coef<T>(d);
   const S* s = static_cast<const S*>(src);
   S* o = static_cast<S*>(dst);
   T* r = static_cast<T*>(rec);
   const dim3 grid = step_grid(g), block(kBlock);
   if (rec) {
-    if (phase == PH_AB) hipLaunchKernelGGL((k_step<S, VEC, MODEL, PH_AB, true>), grid, block, 0, st, s, o, g, k, r, d.plane_t);
-    else if (phase == PH_AA_EVEN) hipLaunchKernelGGL((k_step<S, VEC, MODEL, PH_AA_EVEN, true>), grid, block, 0, st, s, o, g, k, r, d.plane_t);
-    else hipLaunchKernelGGL((k_step<S, VEC, MODEL, PH_AA_ODD, true>), grid, block, 0, st, s, o, g, k, r, d.plane_t);
+    if (phase == PH_AB) hipLaunchKernelGGL((k_step<S, VEC, MODEL, PH_AB, true>), grid, block, 0, st, s, o, g, k, r, d.rs_rec);
+    else if (phase == PH_AA_EVEN) hipLaunchKernelGGL((k_step<S, VEC, MODEL, PH_AA_EVEN, true>), grid, block, 0, st, s, o, g, k, r, d.rs_rec);
+    else hipLaunchKernelGGL((k_step<S, VEC, MODEL, PH_AA_ODD, true>), grid, block, 0, st, s, o, g, k, r, d.rs_rec);
   } else {
-    if (phase == PH_AB) hipLaunchKernelGGL((k_step<S, VEC, MODEL, PH_AB, false>), grid, block, 0, st, s, o, g, k, r, d.plane_t);
-    else if (phase == PH_AA_EVEN) hipLaunchKernelGGL((k_step<S, VEC, MODEL, PH_AA_EVEN, false>), grid, block, 0, st, s, o, g, k, r, d.plane_t);
-    else hipLaunchKernelGGL((k_step<S, VEC, MODEL, PH_AA_ODD, false>), grid, block, 0, st, s, o, g, k, r, d.plane_t);
+    if (phase == PH_AB) hipLaunchKernelGGL((k_step<S, VEC, MODEL, PH_AB, false>), grid, block, 0, st, s, o, g, k, r, d.rs_rec);
+    else if (phase == PH_AA_EVEN) hipLaunchKernelGGL((k_step<S, VEC, MODEL, PH_AA_EVEN, false>), grid, block, 0, st, s, o, g, k, r, d.rs_rec);
+    else hipLaunchKernelGGL((k_step<S, VEC, MODEL, PH_AA_ODD, false>), grid, block, 0, st, s, o, g, k, r, d.rs_rec);
   }
   return hipGetLastError();
 }
@@ -282,21 +283,23 @@ hipError_t launch_step_m(const RunDesc& d, int phase, const void* src, void* dst
   }
 }
 
-// Nodes per thread: 16 bytes of each population per thread (default), or the narrower
-// variants kept for tuning sweeps.
+// Nodes per thread: the default (first) choice was the fastest in sweeps on MI355X; the
+// second is kept for tuning.
 template <class S>
 struct VecChoice;
-template <> struct VecChoice<double> { static constexpr int a = 2, b = 1, c = 1; };
-template <> struct VecChoice<float> { static constexpr int a = 4, b = 2, c = 1; };
-template <> struct VecChoice<_Float16> { static constexpr int a = 8, b = 4, c = 2; };
-template <> struct VecChoice<bf16_t> { static constexpr int a = 8, b = 4, c = 2; };
+template <> struct VecChoice<double> { static constexpr int a = 1, b = 2; };
+template <> struct VecChoice<float> { static constexpr int a = 1, b = 2; };
+template <> struct VecChoice<_Float16> { static constexpr int a = 1, b = 2; };
+template <> struct VecChoice<bf16_t> { static constexpr int a = 1, b = 2; };
+
+template <class S>
+int Engine<S>::default_vec() { return VecChoice<S>::a; }
 
 template <class S>
 hipError_t Engine<S>::step(const RunDesc& d, int phase, const void* src, void* dst, void* rec, hipStream_t st) {
   using V = VecChoice<S>;
   if (d.vec == V::a) return launch_step_m<S, V::a>(d, phase, src, dst, rec, st);
   if (d.vec == V::b) return launch_step_m<S, V::b>(d, phase, src, dst, rec, st);
-  if (d.vec == V::c) return launch_step_m<S, V::c>(d, phase, src, dst, rec, st);
   return hipErrorInvalidValue;
 }
 
@@ -370,15 +373,14 @@ hipError_t Engine<S>::fbar_export(const RunDesc& d, const T* fbar, T* dense, hip
 
 template <class S>
 hipError_t Engine<S>::adjoint_step(const RunDesc& d, const T* fbar_next, T* fbar, const T* rec, hipStream_t st) {
-  constexpr int V = 16 / int(sizeof(T));
-  const Geo g = make_geo(d, V, d.plane_t);
+  const Geo g = make_geo(d, 1);
   const Coef<T> k = make_coef<T>(d);
   const dim3 grid = step_grid(g), block(kBlock);
   switch (d.model) {
-    case M_BGK: hipLaunchKernelGGL((k_adjoint_step<T, V, M_BGK>), grid, block, 0, st, fbar_next, fbar, g, k, rec, d.plane_t); break;
-    case M_UC: hipLaunchKernelGGL((k_adjoint_step<T, V, M_UC>), grid, block, 0, st, fbar_next, fbar, g, k, rec, d.plane_t); break;
-    case M_PARTIAL: hipLaunchKernelGGL((k_adjoint_step<T, V, M_PARTIAL>), grid, block, 0, st, fbar_next, fbar, g, k, rec, d.plane_t); break;
-    default: hipLaunchKernelGGL((k_adjoint_step<T, V, M_COMPLETE>), grid, block, 0, st, fbar_next, fbar, g, k, rec, d.plane_t); break;
+    case M_BGK: hipLaunchKernelGGL((k_adjoint_step<T, 1, M_BGK>), grid, block, 0, st, fbar_next, fbar, g, k, rec, d.rs_rec); break;
+    case M_UC: hipLaunchKernelGGL((k_adjoint_step<T, 1, M_UC>), grid, block, 0, st, fbar_next, fbar, g, k, rec, d.rs_rec); break;
+    case M_PARTIAL: hipLaunchKernelGGL((k_adjoint_step<T, 1, M_PARTIAL>), grid, block, 0, st, fbar_next, fbar, g, k, rec, d.rs_rec); break;
+    default: hipLaunchKernelGGL((k_adjoint_step<T, 1, M_COMPLETE>), grid, block, 0, st, fbar_next, fbar, g, k, rec, d.rs_rec); break;
   }
   return hipGetLastError();
 }
