@@ -204,14 +204,14 @@ def main():
         nt = wt.nx * wt.ny
         ref = None
         for storage in ("f64", "f32", "f16", "bf16"):
-            log(f"[bench] variant turb8192 complete {storage} aa")
-            s = make_sim(wt, "complete", storage, "aa", tf)
+            log(f"[bench] variant turb8192 complete {storage} ab")
+            s = make_sim(wt, "complete", storage, "ab", tf)
             m = time_steps(s, 200, 20)
             ent = {"ms_per_step": m, "GLUPS": nt / (m * 1e-3) / 1e9,
                    "hbm_frac": ALG_BYTES[storage] * nt / (m * 1e-3) / 1e9 / HBM_PEAK_GBS}
             del s
             if args.precision_steps > 0:
-                s = make_sim(wt, "complete", storage, "aa", tf)
+                s = make_sim(wt, "complete", storage, "ab", tf)
                 s.step(args.precision_steps)
                 f = s.populations(dtype=torch.float64)
                 if storage == "f64":
@@ -220,7 +220,7 @@ def main():
                 else:
                     ent[f"eps_f_vs_f64_after_{args.precision_steps}"] = (f - ref).abs().max().item() / fmax
                 del s, f
-            var[f"turb8192/complete/{storage}/aa"] = ent
+            var[f"turb8192/complete/{storage}/ab"] = ent
         del ref, tf
         # Adjoint: the adjoint step kernel at 4096^2 (HBM-bound) and the end-to-end gradient on
         # the 1024^2 advected shear wave (500 steps, sqrt(N) checkpoints).
@@ -242,7 +242,7 @@ def bench_adjoint(inp):
     w = inp.WORKLOADS["tg4096"]
     fields = w.fields(seed=0)
     N = 64
-    sim = make_sim(w, "complete", "f32", "aa", fields, record_steps=N, ckpt_stride=8)
+    sim = make_sim(w, "complete", "f32", "ab", fields, record_steps=N, ckpt_stride=8)
     sim.step(N)
     z = torch.zeros((w.ny, w.nx), dtype=torch.float32, device="cuda")
     sim.adjoint(None, z + 1e-3, z)  # warm-up
@@ -263,7 +263,7 @@ def bench_adjoint(inp):
     wa = inp.WORKLOADS["shear1024"]
     rho, ux, uy = wa.fields(seed=0)
     cfg = dict(nx=wa.nx, ny=wa.ny, theta=wa.theta, nu=wa.nu, steps=wa.steps, model="complete", storage="f32",
-               pattern="aa")
+               pattern="ab")
     t = lambda a: torch.as_tensor(a, dtype=torch.float32, device="cuda")
     for rep in range(2):
         ux0 = t(ux).requires_grad_(True)
@@ -275,7 +275,7 @@ def bench_adjoint(inp):
         E.backward()
         torch.cuda.synchronize()
         dt = time.perf_counter() - t0
-    res["gradient/shear1024/complete/f32/aa"] = {
+    res["gradient/shear1024/complete/f32/ab"] = {
         "steps": wa.steps, "s_total": dt, "GLUPS_end_to_end": wa.nx * wa.ny * wa.steps / dt / 1e9,
         "note": "forward with checkpoints + recomputation + adjoint, cache-resident size"}
     return res

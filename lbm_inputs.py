@@ -79,7 +79,8 @@ def random_phase_turbulence(n, kmin, kmax, u_rms, seed=0, rho0=1.0):
 
     Stream-function modes at integer wave vectors with shell K = round(|k|) in
     [kmin, kmax], amplitude |psi_hat| ~ K^(-7/3), uniform random phases; u = d psi/dy,
-    v = -d psi/dx (spectral derivatives); scaled so that each component has rms u_rms.
+    v = -d psi/dx (spectral derivatives); one common scale factor (which keeps the field
+    divergence-free) sets the rms over both components, sqrt(<u^2 + v^2>/2), to u_rms.
     """
     rng = np.random.default_rng(seed)
     k1 = np.fft.fftfreq(n, d=1.0 / n)
@@ -95,8 +96,9 @@ def random_phase_turbulence(n, kmin, kmax, u_rms, seed=0, rho0=1.0):
     two_pi_over_n = 2 * math.pi / n
     ux = np.fft.ifft2(1j * ky * two_pi_over_n * psi_hat).real
     uy = np.fft.ifft2(-1j * kx * two_pi_over_n * psi_hat).real
-    ux *= u_rms / np.sqrt(np.mean(ux * ux))
-    uy *= u_rms / np.sqrt(np.mean(uy * uy))
+    scale = u_rms / np.sqrt(0.5 * np.mean(ux * ux + uy * uy))
+    ux *= scale
+    uy *= scale
     rho = np.full((n, n), rho0)
     return rho, ux, uy
 

@@ -52,16 +52,17 @@ template <> struct StorageTraits<_Float16> {
   static __device__ __forceinline__ float load(_Float16 v) { return float(v); }
   static __device__ __forceinline__ _Float16 store(float v) { return _Float16(v); }
 };
-// bfloat16 as its raw 16 bits.
+// bfloat16 as its raw 16 bits; stores convert with the hardware FP32 -> BF16 conversion
+// (round to nearest even).
 struct bf16_t { uint16_t bits; };
 template <> struct StorageTraits<bf16_t> {
   using T = float;
   static __device__ __forceinline__ float load(bf16_t v) { return __uint_as_float(uint32_t(v.bits) << 16); }
   static __device__ __forceinline__ bf16_t store(float v) {
-    uint32_t u = __float_as_uint(v);
-    if ((u & 0x7fffffffu) > 0x7f800000u) return bf16_t{uint16_t((u >> 16) | 0x40u)};  // quiet NaN
-    u += 0x7fffu + ((u >> 16) & 1u);
-    return bf16_t{uint16_t(u >> 16)};
+    const __bf16 h = static_cast<__bf16>(v);
+    bf16_t r;
+    __builtin_memcpy(&r.bits, &h, sizeof(r.bits));
+    return r;
   }
 };
 
