@@ -129,6 +129,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--precision-steps", type=int, default=1000,
                     help="steps of the 8192^2 storage-precision comparison")
+    ap.add_argument("--only", choices=["adjoint"], default=None,
+                    help="run only one section (adjoint: sweep and end-to-end gradient) and print its JSON")
     ap.add_argument("--copy-probe", type=int, default=0,
                     help="only run a device-to-device copy of this many bytes (counter scaling)")
     args = ap.parse_args()
@@ -152,6 +154,10 @@ def main():
             b.copy_(a)
         torch.cuda.synchronize()
         log(f"copy probe: 3 x {args.copy_probe} bytes")
+        return
+
+    if args.only == "adjoint":
+        print(json.dumps(bench_adjoint(inp)), flush=True)
         return
 
     w = inp.WORKLOADS[args.workload]
