@@ -42,7 +42,9 @@ class Simulation:
                                    _ptr(rho_t), _ptr(ux_t), _ptr(uy_t))
         capi.check(s, "lbm_init")
         self._ctx = ctx
-        self._keep = (rho_t, ux_t, uy_t)
+        # The init kernel reads the FP64 fields asynchronously; wait once so the caller may
+        # free or reuse them on any stream.
+        self.stream.synchronize()
 
     # -- lifecycle ------------------------------------------------------------------------------
     def close(self):
@@ -86,7 +88,7 @@ class Simulation:
         if tuple(f.shape) != (9,) + self.shape:
             raise ValueError("populations must have shape (9, ny, nx)")
         capi.check(capi.lbm_set_populations(self._ctx, f.data_ptr()), "lbm_set_populations")
-        self._keep_f = f
+        self.stream.synchronize()
         return self
 
     def invariants(self, allow_nonfinite=False):
