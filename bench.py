@@ -129,8 +129,9 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--precision-steps", type=int, default=1000,
                     help="steps of the 8192^2 storage-precision comparison")
-    ap.add_argument("--only", choices=["adjoint"], default=None,
-                    help="run only one section (adjoint: sweep and end-to-end gradient) and print its JSON")
+    ap.add_argument("--only", choices=["adjoint", "precision"], default=None,
+                    help="run only one section and print its JSON (adjoint: sweep and end-to-end gradient; "
+                         "precision: storage types on the 8192^2 turbulence workload against the FP64 run)")
     ap.add_argument("--copy-probe", type=int, default=0,
                     help="only run a device-to-device copy of this many bytes (counter scaling)")
     args = ap.parse_args()
@@ -158,6 +159,9 @@ def main():
 
     if args.only == "adjoint":
         print(json.dumps(bench_adjoint(inp)), flush=True)
+        return
+    if args.only == "precision":
+        print(json.dumps(bench_precision(inp)), flush=True)
         return
 
     w = inp.WORKLOADS[args.workload]
@@ -238,6 +242,51 @@ def main():
             out["cpu_baseline"] = cpu_baseline(w, args.model)
     out["kernel_source_hash"] = kernel_source_hash()
     print(json.dumps(out), flush=True)
+
+
+def bench_precision(inp, checkpoints=(100, 1000, 5000)):
+    """Storage precision on the 8192^2 decaying-turbulence workload (complete model): errors
+    of FP32, FP16 and BF16 storage against the FP64-storage run at the given steps."""
+    import torch
+    w = inp.WORKLOADS["turb8192"]
+    fields = w.fields(seed=0)
+    ref = {}
+    log("[precision] FP64 reference")
+    s = make_sim(w, "complete", "f64", "ab", fields)
+    done = 0
+    for n in checkpoints:
+        s.step(n - done)
+        done = n
+        r, ux, uy = s.moments()
+        ref[n] = dict(f=s.populations(dtype=torch.float32).cpu(), rho=r.cpu(), ux=ux.cpu(), uy=uy.cpu(),
+                      ke=float(0.5 * (r * (ux * ux + uy * uy)).sum()))
+    del s
+    out = {"workload": w.name, "model": "complete", "reference": "FP64 storage, FP64 arithmetic",
+           "ke_reference": {str(n): ref[n]["ke"] for n in checkpoints}}
+    for storage in ("f32", "f16", "bf16"):
+        log(f"[precision] {storage}")
+        s = make_sim(w, "complete", storage, "ab", fields)
+        done = 0
+        res = {}
+        for n in checkpoints:
+            s.step(n - done)
+            done = n
+            r, ux, uy = s.moments()
+            f = s.populations(dtype=torch.float32).cpu()
+            R = ref[n]
+            ke = float(0.5 * (r * (ux * ux + uy * uy)).sum())
+            umax = max(float(R["ux"].abs().max()), float(R["uy"].abs().max()))
+            res[str(n)] = {
+                "eps_f": float((f.double() - R["f"].double()).abs().max() / R["f"].double().abs().max()),
+                "eps_u_inf": max(float((ux.cpu() - R["ux"]).abs().max()), float((uy.cpu() - R["uy"]).abs().max())) / umax,
+                "eps_u_l2": float(torch.sqrt(((ux.cpu() - R["ux"]) ** 2 + (uy.cpu() - R["uy"]) ** 2).sum()
+                                             / (R["ux"] ** 2 + R["uy"] ** 2).sum())),
+                "eps_rho": float((r.cpu() - R["rho"]).abs().max() / (R["rho"] - w.rho0).abs().max()),
+                "ke_rel": ke / R["ke"] - 1.0,
+            }
+        out[storage] = res
+        del s
+    return out
 
 
 def bench_adjoint(inp):

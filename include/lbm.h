@@ -68,7 +68,7 @@ typedef enum { LBM_F64 = 0, LBM_F32 = 1, LBM_BF16 = 2, LBM_F16 = 3 } lbm_dtype;
 typedef enum { LBM_AB = 0, LBM_AA = 1 } lbm_pattern;
 
 typedef struct {
-  int32_t nx, ny;        /* periodic box, 1 <= nx, ny; (nx+7)/8*8*ny < 2^31 */
+  int32_t nx, ny;        /* periodic box, 1 <= nx, ny; (nx+63)/64*64*ny < 2^31 */
   double theta;          /* reduced lattice temperature, 0 < theta < 1 */
   double nu;             /* lattice viscosity > 0; tau = nu/theta + 1/2 (nu = theta (tau - 1/2)) */
   double rho0;           /* reference density > 0 (storage shift) */

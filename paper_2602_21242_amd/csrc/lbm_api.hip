@@ -49,12 +49,14 @@ struct Plan {
   size_t total = 0;
 };
 
+// Elements per population row: nx rounded up to whole 64-node groups (lane-strided rows).
+int64_t row_pitch(int64_t nx) { return (nx + 63) / 64 * 64; }
+
 lbm_status validate(const lbm_params* p) {
   if (!p) return fail(LBM_ERR_INVALID_ARGUMENT, "params is NULL");
   if (p->nx < 1 || p->ny < 1) return fail(LBM_ERR_INVALID_ARGUMENT, "nx and ny must be >= 1");
-  const int64_t pitch = (int64_t(p->nx) + 7) / 8 * 8;
-  if (pitch * int64_t(p->ny) >= (int64_t(1) << 31))
-    return fail(LBM_ERR_INVALID_ARGUMENT, "grid too large: (nx rounded up to 8) * ny must be < 2^31");
+  if (row_pitch(p->nx) * int64_t(p->ny) >= (int64_t(1) << 31))
+    return fail(LBM_ERR_INVALID_ARGUMENT, "grid too large: (nx rounded up to 64) * ny must be < 2^31");
   if (!(p->theta > 0.0 && p->theta < 1.0)) return fail(LBM_ERR_INVALID_ARGUMENT, "theta must lie in (0, 1)");
   if (!(p->nu > 0.0) || !std::isfinite(p->nu)) return fail(LBM_ERR_INVALID_ARGUMENT, "nu must be finite and > 0");
   if (!(p->rho0 > 0.0) || !std::isfinite(p->rho0)) return fail(LBM_ERR_INVALID_ARGUMENT, "rho0 must be finite and > 0");
@@ -70,7 +72,7 @@ Plan make_plan(const lbm_params& p) {
   Plan pl;
   pl.esize = storage_size(p.storage);
   pl.tsize = p.storage == LBM_F64 ? 8 : 4;
-  const size_t pitch = (size_t(p.nx) + 7) / 8 * 8;
+  const size_t pitch = size_t(row_pitch(p.nx));
   // Row-interleaved buffers: ny rows of nine (populations) or five (recorded moments)
   // population rows of `pitch` elements each, rounded up to 4 KiB.
   pl.pop_bytes = round_up(size_t(lbm::Q) * pitch * p.ny * pl.esize, 4096);
@@ -241,23 +243,6 @@ lbm_status guarded(F&& f) {
   }
 }
 
-// Nodes per thread of the step kernel: the engine's default, or LBM_VEC (tuning sweeps;
-// must name one of the widths the engine instantiates).
-int dispatch_vec(int storage) {
-  int v = 1;
-  switch (storage) {
-    case LBM_F64: v = lbm::Engine<double>::default_vec(); break;
-    case LBM_F32: v = lbm::Engine<float>::default_vec(); break;
-    case LBM_F16: v = lbm::Engine<_Float16>::default_vec(); break;
-    default: v = lbm::Engine<lbm::bf16_t>::default_vec(); break;
-  }
-  if (const char* s = std::getenv("LBM_VEC")) {
-    const int w = std::atoi(s);
-    if (w > 0) v = w;
-  }
-  return v;
-}
-
 }  // namespace
 
 extern "C" {
@@ -296,7 +281,7 @@ lbm_status lbm_init(const lbm_params* p, void* d_workspace, size_t workspace_byt
     lbm::RunDesc& d = c->d;
     d.nx = p->nx;
     d.ny = p->ny;
-    d.pitch = int((p->nx + 7) / 8 * 8);
+    d.pitch = int(row_pitch(p->nx));
     d.rs = int64_t(lbm::Q) * d.pitch;
     d.rs_rec = int64_t(lbm::NREC) * d.pitch;
     d.theta = p->theta;
@@ -304,7 +289,6 @@ lbm_status lbm_init(const lbm_params* p, void* d_workspace, size_t workspace_byt
     d.rho0 = p->rho0;
     d.tau = p->nu / p->theta + 0.5;  // nu = theta (tau - 1/2)
     d.model = p->model;
-    d.vec = dispatch_vec(p->storage);
     c->time = 0;
     c->cur = 0;
     c->rec_valid = p->record_steps > 0;

@@ -73,7 +73,7 @@ struct Coef {
   T rho0;
   T omb;          // 1 - 1/tau
   T omb_inv2th2;  // (1 - 1/tau)/(2 theta^2)
-  T r0, r1;       // rest factors 1 - theta, theta/2
+  T r0, r1;       // rest factors 1 - theta, theta/2, rounded so that r0 + 2 r1 == 1 exactly
   T rr0, rr1;     // rho0 r0, rho0 r1
   T inv2th2;      // 1/(2 theta^2)
   T inv4th2;      // 1/(4 theta^2)

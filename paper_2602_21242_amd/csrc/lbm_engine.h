@@ -12,14 +12,14 @@
 namespace lbm {
 
 // Everything a launcher needs to know about a run (host side).
-// Every buffer is row-interleaved: element (i, x, y) at y * row_stride + i * pitch + x.
+// Every buffer is row-interleaved and lane-strided within a row: element (i, x, y) at
+// y * row_stride + i * pitch + pos(x), pos(x) = (x mod S) * 64 + floor(x / S), S = pitch / 64.
 struct RunDesc {
-  int nx, ny, pitch;  // pitch = nx rounded up to 8
+  int nx, ny, pitch;  // pitch = 64 ceil(nx / 64)
   int64_t rs;         // row stride of the populations and of fbar (9 * pitch)
   int64_t rs_rec;     // row stride of a recorded-moment slot (5 * pitch)
   double theta, nu, rho0, tau;
   int model;         // M_BGK ... M_COMPLETE
-  int vec;           // nodes per thread of the step kernel
 };
 
 // State layout at a given time: f_i(x) = buf[swap ? opp(i) : i][x - shift c_i].
@@ -32,7 +32,6 @@ constexpr int kReduceBlocks = 1024;  // partial sums of the FP64 invariants
 template <class S>
 struct Engine {
   using T = typename StorageTraits<S>::T;
-  static int default_vec();
   static hipError_t step(const RunDesc& d, int phase, const void* src, void* dst, void* rec, hipStream_t st);
   static hipError_t init(const RunDesc& d, LayoutSel L, void* buf, const double* rho, const double* ux,
                          const double* uy, hipStream_t st);
@@ -59,10 +58,21 @@ inline Coef<T> make_coef(const RunDesc& d) {
   k.rho0 = T(d.rho0);
   k.omb = T(1.0 - 1.0 / d.tau);
   k.omb_inv2th2 = T((1.0 - 1.0 / d.tau) / (2.0 * th * th));
-  k.r0 = T(1.0 - th);
-  k.r1 = T(0.5 * th);
-  k.rr0 = T(d.rho0 * (1.0 - th));
-  k.rr1 = T(d.rho0 * 0.5 * th);
+  // Per-axis rest factors with r0 + 2 r1 == 1 exactly in T. The product equilibrium carries
+  // momentum rho u (r0 + 2 r1) and density excess drho (r0 + 2 r1)^2, so a rounding excess
+  // e = r0 + 2 r1 - 1 would scale the momentum field by 1 + e every step (1 + e/tau for LBGK):
+  // with FP32 at theta = 1/3, e = 3e-8 and the kinetic energy gains 6e-5 per 1000 steps. The
+  // difference that forms the second factor is exact (Sterbenz): 1 - r0 for r0 >= 1/2, and
+  // 1 - 2 r1 for 2 r1 >= 1/2.
+  if (th <= 0.5) {
+    k.r0 = T(1.0 - th);
+    k.r1 = (T(1) - k.r0) * T(0.5);
+  } else {
+    k.r1 = T(0.5 * th);
+    k.r0 = T(1) - T(2) * k.r1;
+  }
+  k.rr0 = T(d.rho0 * double(k.r0));
+  k.rr1 = T(d.rho0 * double(k.r1));
   k.inv2th2 = T(1.0 / (2.0 * th * th));
   k.inv4th2 = T(1.0 / (4.0 * th * th));
   k.a0 = T(th * (1.0 - 3.0 * th));

@@ -10,13 +10,17 @@ namespace lbm {
 
 // --- geometry -----------------------------------------------------------------------------
 
-inline Geo make_geo(const RunDesc& d, int vec) {
+__host__ __device__ __forceinline__ int row_pos(int x, int S) { return (x % S) * kLanes + x / S; }
+
+inline Geo make_geo(const RunDesc& d) {
   Geo g;
   g.nx = d.nx;
   g.ny = d.ny;
+  g.S = d.pitch / kLanes;
   g.ps = d.pitch;
   g.rs = d.rs;
-  g.nseg = ((d.nx + vec - 1) / vec + kBlock - 1) / kBlock;
+  g.nseg = (d.pitch + kBlock - 1) / kBlock;
+  g.plast = row_pos(d.nx - 1, g.S);
   return g;
 }
 
@@ -24,16 +28,32 @@ inline dim3 step_grid(const Geo& g) {
   return dim3(unsigned(g.nseg), unsigned(std::min(g.ny, kRowsY)), unsigned((g.ny + kRowsY - 1) / kRowsY));
 }
 
-inline int node_blocks(const RunDesc& d) { return int((int64_t(d.nx) * d.ny + kBlock - 1) / kBlock); }
+// The auxiliary kernels run one thread per storage position (pitch * ny of them), so their
+// nine population accesses are coalesced; the dense [ny][nx] fields are indexed by node.
+inline int node_blocks(const RunDesc& d) { return int((int64_t(d.pitch) * d.ny + kBlock - 1) / kBlock); }
 
-__device__ __forceinline__ int64_t layout_index(int i, int x, int y, int nx, int ny, int pitch, int64_t rs,
-                                                LayoutSel L) {
+// Storage position t (row y, in-row position q) -> node x; false for padding and past the end.
+__device__ __forceinline__ bool storage_node(int64_t t, const RunDesc& d, int& y, int& q, int& x) {
+  if (t >= int64_t(d.pitch) * d.ny) return false;
+  y = int(t / d.pitch);
+  q = int(t - int64_t(y) * d.pitch);
+  x = (q % kLanes) * (d.pitch / kLanes) + q / kLanes;
+  return x < d.nx;
+}
+
+// Buffer index of population i of node (x, y) under a stored-state convention L.
+__device__ __forceinline__ int64_t layout_index(int i, int x, int y, const RunDesc& d, LayoutSel L) {
   const int slot = L.swap ? opp(i) : i;
   int xs = x - L.shift * cx(i);
-  xs = xs < 0 ? xs + nx : (xs >= nx ? xs - nx : xs);
+  xs = xs < 0 ? xs + d.nx : (xs >= d.nx ? xs - d.nx : xs);
   int ys = y - L.shift * cy(i);
-  ys = ys < 0 ? ys + ny : (ys >= ny ? ys - ny : ys);
-  return int64_t(ys) * rs + slot * pitch + xs;
+  ys = ys < 0 ? ys + d.ny : (ys >= d.ny ? ys - d.ny : ys);
+  return int64_t(ys) * d.rs + slot * d.pitch + row_pos(xs, d.pitch / kLanes);
+}
+
+// Buffer index of entry i of node (x, y) stored at in-row position q (no shift).
+__device__ __forceinline__ int64_t local_index(int i, int q, int y, const RunDesc& d) {
+  return int64_t(y) * d.rs + i * d.pitch + q;
 }
 
 // --- per-node auxiliary kernels --------------------------------------------------------------
@@ -44,9 +64,9 @@ template <class S>
 __global__ void __launch_bounds__(kBlock)
 k_init(S* buf, RunDesc d, LayoutSel L, const double* rho, const double* ux, const double* uy) {
   using Tr = StorageTraits<S>;
-  const int64_t n = int64_t(blockIdx.x) * kBlock + threadIdx.x;
-  if (n >= int64_t(d.nx) * d.ny) return;
-  const int y = int(n / d.nx), x = int(n - int64_t(y) * d.nx);
+  int y, q, x;
+  if (!storage_node(int64_t(blockIdx.x) * kBlock + threadIdx.x, d, y, q, x)) return;
+  const int64_t n = int64_t(y) * d.nx + x;
   const double r = rho ? rho[n] : d.rho0;
   const double vx = ux[n], vy = uy[n];
   const double drho = r - d.rho0;
@@ -59,7 +79,7 @@ k_init(S* buf, RunDesc d, LayoutSel L, const double* rho, const double* ux, cons
     const int a = cx(i) + 1, b = cy(i) + 1;
     const double hx = rr[a] + dx[a], hy = rr[b] + dy[b];
     const double feqs = drho * hx * hy + d.rho0 * (dx[a] * hy + rr[a] * dy[b]);
-    buf[layout_index(i, x, y, d.nx, d.ny, d.pitch, d.rs, L)] = Tr::store(typename Tr::T(feqs));
+    buf[layout_index(i, x, y, d, L)] = Tr::store(typename Tr::T(feqs));
   }
 }
 
@@ -68,14 +88,14 @@ __global__ void __launch_bounds__(kBlock)
 k_get(const S* buf, RunDesc d, LayoutSel L, O* out) {
   using Tr = StorageTraits<S>;
   const int64_t N = int64_t(d.nx) * d.ny;
-  const int64_t n = int64_t(blockIdx.x) * kBlock + threadIdx.x;
-  if (n >= N) return;
-  const int y = int(n / d.nx), x = int(n - int64_t(y) * d.nx);
+  int y, q, x;
+  if (!storage_node(int64_t(blockIdx.x) * kBlock + threadIdx.x, d, y, q, x)) return;
+  const int64_t n = int64_t(y) * d.nx + x;
   const double th = d.theta;
 #pragma unroll
   for (int i = 0; i < Q; ++i) {
     const double w = (cx(i) == 0 ? 1.0 - th : 0.5 * th) * (cy(i) == 0 ? 1.0 - th : 0.5 * th);
-    const double g = double(Tr::load(buf[layout_index(i, x, y, d.nx, d.ny, d.pitch, d.rs, L)]));
+    const double g = double(Tr::load(buf[layout_index(i, x, y, d, L)]));
     out[i * N + n] = O(g + w * d.rho0);
   }
 }
@@ -85,14 +105,14 @@ __global__ void __launch_bounds__(kBlock)
 k_set(S* buf, RunDesc d, LayoutSel L, const double* in) {
   using Tr = StorageTraits<S>;
   const int64_t N = int64_t(d.nx) * d.ny;
-  const int64_t n = int64_t(blockIdx.x) * kBlock + threadIdx.x;
-  if (n >= N) return;
-  const int y = int(n / d.nx), x = int(n - int64_t(y) * d.nx);
+  int y, q, x;
+  if (!storage_node(int64_t(blockIdx.x) * kBlock + threadIdx.x, d, y, q, x)) return;
+  const int64_t n = int64_t(y) * d.nx + x;
   const double th = d.theta;
 #pragma unroll
   for (int i = 0; i < Q; ++i) {
     const double w = (cx(i) == 0 ? 1.0 - th : 0.5 * th) * (cy(i) == 0 ? 1.0 - th : 0.5 * th);
-    buf[layout_index(i, x, y, d.nx, d.ny, d.pitch, d.rs, L)] = Tr::store(typename Tr::T(in[i * N + n] - w * d.rho0));
+    buf[layout_index(i, x, y, d, L)] = Tr::store(typename Tr::T(in[i * N + n] - w * d.rho0));
   }
 }
 
@@ -105,7 +125,7 @@ __device__ __forceinline__ void node_moments(const S* buf, const RunDesc& d, Lay
   bool nf = false;
 #pragma unroll
   for (int i = 0; i < Q; ++i) {
-    const double g = double(Tr::load(buf[layout_index(i, x, y, d.nx, d.ny, d.pitch, d.rs, L)]));
+    const double g = double(Tr::load(buf[layout_index(i, x, y, d, L)]));
     nf |= !isfinite(g);
     drho += g;
     jx += cx(i) * g;
@@ -117,9 +137,9 @@ __device__ __forceinline__ void node_moments(const S* buf, const RunDesc& d, Lay
 template <class S, class O>
 __global__ void __launch_bounds__(kBlock)
 k_moments(const S* buf, RunDesc d, LayoutSel L, O* rho, O* ux, O* uy) {
-  const int64_t n = int64_t(blockIdx.x) * kBlock + threadIdx.x;
-  if (n >= int64_t(d.nx) * d.ny) return;
-  const int y = int(n / d.nx), x = int(n - int64_t(y) * d.nx);
+  int y, q, x;
+  if (!storage_node(int64_t(blockIdx.x) * kBlock + threadIdx.x, d, y, q, x)) return;
+  const int64_t n = int64_t(y) * d.nx + x;
   double drho, jx, jy;
   node_moments(buf, d, L, x, y, drho, jx, jy);
   const double r = d.rho0 + drho;
@@ -133,10 +153,11 @@ template <class S>
 __global__ void __launch_bounds__(kBlock)
 k_reduce_partial(const S* buf, RunDesc d, LayoutSel L, double* partial) {
   __shared__ double sh[4][kBlock];
-  const int64_t N = int64_t(d.nx) * d.ny;
+  const int64_t T = int64_t(d.pitch) * d.ny;
   double s0 = 0, s1 = 0, s2 = 0, s3 = 0;
-  for (int64_t n = int64_t(blockIdx.x) * kBlock + threadIdx.x; n < N; n += int64_t(gridDim.x) * kBlock) {
-    const int y = int(n / d.nx), x = int(n - int64_t(y) * d.nx);
+  for (int64_t t = int64_t(blockIdx.x) * kBlock + threadIdx.x; t < T; t += int64_t(gridDim.x) * kBlock) {
+    int y, q, x;
+    if (!storage_node(t, d, y, q, x)) continue;
     double drho, jx, jy;
     bool bad;
     node_moments(buf, d, L, x, y, drho, jx, jy, &bad);
@@ -186,9 +207,9 @@ k_reduce_final(const double* partial, int nparts, double mass_offset, double* re
 template <class S, class T>
 __global__ void __launch_bounds__(kBlock)
 k_seed(const S* buf, RunDesc d, LayoutSel L, const T* rhob, const T* uxb, const T* uyb, T* fbar) {
-  const int64_t n = int64_t(blockIdx.x) * kBlock + threadIdx.x;
-  if (n >= int64_t(d.nx) * d.ny) return;
-  const int y = int(n / d.nx), x = int(n - int64_t(y) * d.nx);
+  int y, q, x;
+  if (!storage_node(int64_t(blockIdx.x) * kBlock + threadIdx.x, d, y, q, x)) return;
+  const int64_t n = int64_t(y) * d.nx + x;
   double drho, jx, jy;
   node_moments(buf, d, L, x, y, drho, jx, jy);
   const T r = T(d.rho0 + drho);
@@ -197,27 +218,27 @@ k_seed(const S* buf, RunDesc d, LayoutSel L, const T* rhob, const T* uxb, const 
   const T ax = uxb[n] / r, ay = uyb[n] / r;
 #pragma unroll
   for (int i = 0; i < Q; ++i)
-    fbar[int64_t(y) * d.rs + i * d.pitch + x] = rb + ax * (T(cx(i)) - vx) + ay * (T(cy(i)) - vy);
+    fbar[local_index(i, q, y, d)] = rb + ax * (T(cx(i)) - vx) + ay * (T(cy(i)) - vy);
 }
 
 template <class T>
 __global__ void __launch_bounds__(kBlock) k_fbar_import(RunDesc d, const T* dense, T* fbar) {
   const int64_t N = int64_t(d.nx) * d.ny;
-  const int64_t n = int64_t(blockIdx.x) * kBlock + threadIdx.x;
-  if (n >= N) return;
-  const int y = int(n / d.nx), x = int(n - int64_t(y) * d.nx);
+  int y, q, x;
+  if (!storage_node(int64_t(blockIdx.x) * kBlock + threadIdx.x, d, y, q, x)) return;
+  const int64_t n = int64_t(y) * d.nx + x;
 #pragma unroll
-  for (int i = 0; i < Q; ++i) fbar[int64_t(y) * d.rs + i * d.pitch + x] = dense[i * N + n];
+  for (int i = 0; i < Q; ++i) fbar[local_index(i, q, y, d)] = dense[i * N + n];
 }
 
 template <class T>
 __global__ void __launch_bounds__(kBlock) k_fbar_export(RunDesc d, const T* fbar, T* dense) {
   const int64_t N = int64_t(d.nx) * d.ny;
-  const int64_t n = int64_t(blockIdx.x) * kBlock + threadIdx.x;
-  if (n >= N) return;
-  const int y = int(n / d.nx), x = int(n - int64_t(y) * d.nx);
+  int y, q, x;
+  if (!storage_node(int64_t(blockIdx.x) * kBlock + threadIdx.x, d, y, q, x)) return;
+  const int64_t n = int64_t(y) * d.nx + x;
 #pragma unroll
-  for (int i = 0; i < Q; ++i) dense[i * N + n] = fbar[int64_t(y) * d.rs + i * d.pitch + x];
+  for (int i = 0; i < Q; ++i) dense[i * N + n] = fbar[local_index(i, q, y, d)];
 }
 
 // Initial-condition adjoint: f^0 = f^eq(rho0_field, u0) with rho held fixed, so
@@ -226,9 +247,9 @@ __global__ void __launch_bounds__(kBlock) k_fbar_export(RunDesc d, const T* fbar
 template <class S, class T>
 __global__ void __launch_bounds__(kBlock)
 k_ic_adjoint(const S* buf0, RunDesc d, LayoutSel L, const T* fbar, T* uxb, T* uyb) {
-  const int64_t n = int64_t(blockIdx.x) * kBlock + threadIdx.x;
-  if (n >= int64_t(d.nx) * d.ny) return;
-  const int y = int(n / d.nx), x = int(n - int64_t(y) * d.nx);
+  int y, q, x;
+  if (!storage_node(int64_t(blockIdx.x) * kBlock + threadIdx.x, d, y, q, x)) return;
+  const int64_t n = int64_t(y) * d.nx + x;
   double drho, jx, jy;
   node_moments(buf0, d, L, x, y, drho, jx, jy);
   const T r = T(d.rho0 + drho);
@@ -242,7 +263,7 @@ k_ic_adjoint(const S* buf0, RunDesc d, LayoutSel L, const T* fbar, T* uxb, T* uy
 #pragma unroll
   for (int i = 0; i < Q; ++i) {
     const int a = cx(i) + 1, b = cy(i) + 1;
-    const T fb = fbar[int64_t(y) * d.rs + i * d.pitch + x];
+    const T fb = fbar[local_index(i, q, y, d)];
     ax += fb * r * gx[a] * hy[b];
     ay += fb * r * hx[a] * gy[b];
   }
@@ -252,55 +273,35 @@ k_ic_adjoint(const S* buf0, RunDesc d, LayoutSel L, const T* fbar, T* uxb, T* uy
 
 // --- step dispatch ---------------------------------------------------------------------------
 
-template <class S, int VEC, int MODEL>
-hipError_t launch_step_v(const RunDesc& d, int phase, const void* src, void* dst, void* rec, hipStream_t st) {
+template <class S, int MODEL>
+hipError_t launch_step_m(const RunDesc& d, int phase, const void* src, void* dst, void* rec, hipStream_t st) {
   using T = typename StorageTraits<S>::T;
-  const Geo g = make_geo(d, VEC);
+  const Geo g = make_geo(d);
   const Coef<T> k = make_coef<T>(d);
   const S* s = static_cast<const S*>(src);
   S* o = static_cast<S*>(dst);
   T* r = static_cast<T*>(rec);
   const dim3 grid = step_grid(g), block(kBlock);
   if (rec) {
-    if (phase == PH_AB) hipLaunchKernelGGL((k_step<S, VEC, MODEL, PH_AB, true>), grid, block, 0, st, s, o, g, k, r, d.rs_rec);
-    else if (phase == PH_AA_EVEN) hipLaunchKernelGGL((k_step<S, VEC, MODEL, PH_AA_EVEN, true>), grid, block, 0, st, s, o, g, k, r, d.rs_rec);
-    else hipLaunchKernelGGL((k_step<S, VEC, MODEL, PH_AA_ODD, true>), grid, block, 0, st, s, o, g, k, r, d.rs_rec);
+    if (phase == PH_AB) hipLaunchKernelGGL((k_step<S, MODEL, PH_AB, true>), grid, block, 0, st, s, o, g, k, r, d.rs_rec);
+    else if (phase == PH_AA_EVEN) hipLaunchKernelGGL((k_step<S, MODEL, PH_AA_EVEN, true>), grid, block, 0, st, s, o, g, k, r, d.rs_rec);
+    else hipLaunchKernelGGL((k_step<S, MODEL, PH_AA_ODD, true>), grid, block, 0, st, s, o, g, k, r, d.rs_rec);
   } else {
-    if (phase == PH_AB) hipLaunchKernelGGL((k_step<S, VEC, MODEL, PH_AB, false>), grid, block, 0, st, s, o, g, k, r, d.rs_rec);
-    else if (phase == PH_AA_EVEN) hipLaunchKernelGGL((k_step<S, VEC, MODEL, PH_AA_EVEN, false>), grid, block, 0, st, s, o, g, k, r, d.rs_rec);
-    else hipLaunchKernelGGL((k_step<S, VEC, MODEL, PH_AA_ODD, false>), grid, block, 0, st, s, o, g, k, r, d.rs_rec);
+    if (phase == PH_AB) hipLaunchKernelGGL((k_step<S, MODEL, PH_AB, false>), grid, block, 0, st, s, o, g, k, r, d.rs_rec);
+    else if (phase == PH_AA_EVEN) hipLaunchKernelGGL((k_step<S, MODEL, PH_AA_EVEN, false>), grid, block, 0, st, s, o, g, k, r, d.rs_rec);
+    else hipLaunchKernelGGL((k_step<S, MODEL, PH_AA_ODD, false>), grid, block, 0, st, s, o, g, k, r, d.rs_rec);
   }
   return hipGetLastError();
 }
 
-template <class S, int VEC>
-hipError_t launch_step_m(const RunDesc& d, int phase, const void* src, void* dst, void* rec, hipStream_t st) {
-  switch (d.model) {
-    case M_BGK: return launch_step_v<S, VEC, M_BGK>(d, phase, src, dst, rec, st);
-    case M_UC: return launch_step_v<S, VEC, M_UC>(d, phase, src, dst, rec, st);
-    case M_PARTIAL: return launch_step_v<S, VEC, M_PARTIAL>(d, phase, src, dst, rec, st);
-    default: return launch_step_v<S, VEC, M_COMPLETE>(d, phase, src, dst, rec, st);
-  }
-}
-
-// Nodes per thread: the default (first) choice was the fastest in sweeps on MI355X; the
-// second is kept for tuning.
-template <class S>
-struct VecChoice;
-template <> struct VecChoice<double> { static constexpr int a = 1, b = 2; };
-template <> struct VecChoice<float> { static constexpr int a = 1, b = 2; };
-template <> struct VecChoice<_Float16> { static constexpr int a = 1, b = 2; };
-template <> struct VecChoice<bf16_t> { static constexpr int a = 1, b = 2; };
-
-template <class S>
-int Engine<S>::default_vec() { return VecChoice<S>::a; }
-
 template <class S>
 hipError_t Engine<S>::step(const RunDesc& d, int phase, const void* src, void* dst, void* rec, hipStream_t st) {
-  using V = VecChoice<S>;
-  if (d.vec == V::a) return launch_step_m<S, V::a>(d, phase, src, dst, rec, st);
-  if (d.vec == V::b) return launch_step_m<S, V::b>(d, phase, src, dst, rec, st);
-  return hipErrorInvalidValue;
+  switch (d.model) {
+    case M_BGK: return launch_step_m<S, M_BGK>(d, phase, src, dst, rec, st);
+    case M_UC: return launch_step_m<S, M_UC>(d, phase, src, dst, rec, st);
+    case M_PARTIAL: return launch_step_m<S, M_PARTIAL>(d, phase, src, dst, rec, st);
+    default: return launch_step_m<S, M_COMPLETE>(d, phase, src, dst, rec, st);
+  }
 }
 
 template <class S>
@@ -373,14 +374,14 @@ hipError_t Engine<S>::fbar_export(const RunDesc& d, const T* fbar, T* dense, hip
 
 template <class S>
 hipError_t Engine<S>::adjoint_step(const RunDesc& d, const T* fbar_next, T* fbar, const T* rec, hipStream_t st) {
-  const Geo g = make_geo(d, 1);
+  const Geo g = make_geo(d);
   const Coef<T> k = make_coef<T>(d);
   const dim3 grid = step_grid(g), block(kBlock);
   switch (d.model) {
-    case M_BGK: hipLaunchKernelGGL((k_adjoint_step<T, 1, M_BGK>), grid, block, 0, st, fbar_next, fbar, g, k, rec, d.rs_rec); break;
-    case M_UC: hipLaunchKernelGGL((k_adjoint_step<T, 1, M_UC>), grid, block, 0, st, fbar_next, fbar, g, k, rec, d.rs_rec); break;
-    case M_PARTIAL: hipLaunchKernelGGL((k_adjoint_step<T, 1, M_PARTIAL>), grid, block, 0, st, fbar_next, fbar, g, k, rec, d.rs_rec); break;
-    default: hipLaunchKernelGGL((k_adjoint_step<T, 1, M_COMPLETE>), grid, block, 0, st, fbar_next, fbar, g, k, rec, d.rs_rec); break;
+    case M_BGK: hipLaunchKernelGGL((k_adjoint_step<T, M_BGK>), grid, block, 0, st, fbar_next, fbar, g, k, rec, d.rs_rec); break;
+    case M_UC: hipLaunchKernelGGL((k_adjoint_step<T, M_UC>), grid, block, 0, st, fbar_next, fbar, g, k, rec, d.rs_rec); break;
+    case M_PARTIAL: hipLaunchKernelGGL((k_adjoint_step<T, M_PARTIAL>), grid, block, 0, st, fbar_next, fbar, g, k, rec, d.rs_rec); break;
+    default: hipLaunchKernelGGL((k_adjoint_step<T, M_COMPLETE>), grid, block, 0, st, fbar_next, fbar, g, k, rec, d.rs_rec); break;
   }
   return hipGetLastError();
 }

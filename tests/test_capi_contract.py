@@ -56,7 +56,7 @@ def _round_up(v, a):
 @pytest.mark.parametrize("pattern,nbuf", [("ab", 2), ("aa", 1)])
 def test_workspace_plan(capi, storage, esize, tsize, pattern, nbuf):
     nx, ny = 37, 11
-    pitch = _round_up(nx, 8)
+    pitch = _round_up(nx, 64)  # rows of whole 64-node groups
     pop = _round_up(9 * pitch * ny * esize, 4096)
     s, n = capi.lbm_workspace_bytes(_params(capi, nx=nx, ny=ny, storage=storage, pattern=pattern))
     assert s == capi.LBM_OK
@@ -76,7 +76,15 @@ def test_workspace_plan(capi, storage, esize, tsize, pattern, nbuf):
 BAD = [dict(nx=0), dict(ny=0), dict(nx=-3), dict(theta=0.0), dict(theta=1.0), dict(theta=float("nan")),
        dict(nu=0.0), dict(nu=-1e-3), dict(nu=float("inf")), dict(rho0=0.0), dict(model=4), dict(model=-1),
        dict(storage=4), dict(pattern=2), dict(record_steps=-1), dict(ckpt_stride=-2),
-       dict(nx=65536, ny=32768)]
+       dict(nx=65536, ny=32768), dict(nx=65537, ny=32767), dict(nx=2 ** 31 - 63, ny=1)]
+
+
+@pytest.mark.parametrize("nx,ny", [(65536, 32767), (2 ** 31 - 64, 1), (1, 2 ** 25 - 1)])
+def test_largest_accepted_grids(capi, nx, ny):
+    """The padded plane (nx rounded up to 64) * ny must stay below 2^31."""
+    s, n = capi.lbm_workspace_bytes(_params(capi, nx=nx, ny=ny, storage="f16", pattern="aa"))
+    assert s == capi.LBM_OK
+    assert n >= 9 * 2 * _round_up(nx, 64) * ny
 
 
 @pytest.mark.parametrize("bad", BAD)
