@@ -77,8 +77,10 @@ struct Coef {
   T rr0, rr1;     // rho0 r0, rho0 r1
   T inv2th2;      // 1/(2 theta^2)
   T inv4th2;      // 1/(4 theta^2)
+  T inv8th2;      // 1/(8 theta^2)
   T a0;           // theta (1 - 3 theta)
-  T wr[Q];        // w_i rho0
+  T b0;           // 2 theta (1 - theta)
+  T c3;           // 1 - 3 theta
 };
 
 // Moments recorded per node and step for the adjoint: rho, u_x, u_y, N_xx, N_xy.
@@ -97,12 +99,21 @@ __device__ __forceinline__ float recip<float>(float x) {
 // ---------------------------------------------------------------------------------------
 // Collision of one node on shifted populations: g -> g* (eq:lbe, first line, with the
 // non-equilibrium part of the chosen model). Optionally returns the recorded moments.
+//
+// The arithmetic is arranged for few vector instructions (the 16-bit storage paths are
+// ALU-bound): the moments come from pair sums; the equilibrium and f^OReg share the
+// product Phi_x Phi_y, g*_i = P_i (drho + t_i) + E_i + Psi_i; and the moments of f^OReg that
+// the corrections need (psi and the prefactor's sum) use their closed forms in N_xx and u,
+// which follow from the per-axis moments of Phi: sum Phi = 1, sum c Phi = u,
+// sum c^2 Phi = theta + u^2, and c^3 = c, c^4 = c^2 on {-1, 0, 1}.
 template <class T, int MODEL>
 __device__ __forceinline__ void collide(const T g[Q], T out[Q], const Coef<T>& k, T rec[NREC]) {
   // Moments (Sec. 1): rho = rho0 + sum g, j = sum c g, D = sum (cx^2 - cy^2) g, Pxy = sum cx cy g.
-  const T drho = ((g[0] + g[1]) + (g[2] + g[3])) + ((g[4] + g[5]) + (g[6] + g[7])) + g[8];
-  const T jx = (g[1] - g[3]) + (g[5] - g[6]) + (g[8] - g[7]);
-  const T jy = (g[2] - g[4]) + (g[5] - g[7]) + (g[6] - g[8]);
+  const T s13 = g[1] + g[3], s24 = g[2] + g[4], s57 = g[5] + g[7], s68 = g[6] + g[8];
+  const T d57 = g[5] - g[7], d68 = g[6] - g[8];
+  const T drho = (g[0] + (s13 + s24)) + (s57 + s68);
+  const T jx = (g[1] - g[3]) + (d57 - d68);
+  const T jy = (g[2] - g[4]) + (d57 + d68);
   const T rho = k.rho0 + drho;
   const T rinv = recip(rho);
   const T ux = jx * rinv, uy = jy * rinv;
@@ -110,20 +121,23 @@ __device__ __forceinline__ void collide(const T g[Q], T out[Q], const Coef<T>& k
 
   // Guided equilibrium (eq:guidedEq) as a product of per-axis factors
   // Phi(0,u) = 1 - theta - u^2, Phi(+-1,u) = (theta + u^2 +- u)/2, written as rest value + d.
-  const T dx0 = -ux2, dxp = T(0.5) * (ux2 + ux), dxm = T(0.5) * (ux2 - ux);
-  const T dy0 = -uy2, dyp = T(0.5) * (uy2 + uy), dym = T(0.5) * (uy2 - uy);
+  const T hux = T(0.5) * ux, huy = T(0.5) * uy, hux2 = T(0.5) * ux2, huy2 = T(0.5) * uy2;
+  const T dx0 = -ux2, dxp = hux2 + hux, dxm = hux2 - hux;
+  const T dy0 = -uy2, dyp = huy2 + huy, dym = huy2 - huy;
   const T hx0 = k.r0 + dx0, hxp = k.r1 + dxp, hxm = k.r1 + dxm;
   const T hy0 = k.r0 + dy0, hyp = k.r1 + dyp, hym = k.r1 + dym;
-
-  T P[Q], feqs[Q];
+  // f_i^eq - w_i rho0 = drho P_i + E_i with P_i = Phi_x Phi_y and
+  // E_i = rho0 (d_x Phi_y + r_x d_y), free of cancellation against w_i rho0.
+  const T rdx0 = k.rho0 * dx0, rdxp = k.rho0 * dxp, rdxm = k.rho0 * dxm;
+  const T a0m = k.rr0 * dym, a00 = k.rr0 * dy0, a0p = k.rr0 * dyp;  // rho0 r_x d_y, c_x = 0
+  const T a1m = k.rr1 * dym, a10 = k.rr1 * dy0, a1p = k.rr1 * dyp;  // rho0 r_x d_y, c_x = +-1
+  T P[Q], E[Q];
 #pragma unroll
   for (int i = 0; i < Q; ++i) {
     const T hx = sel(cx(i), hxm, hx0, hxp), hy = sel(cy(i), hym, hy0, hyp);
-    const T dxi = sel(cx(i), dxm, dx0, dxp), dyi = sel(cy(i), dym, dy0, dyp);
-    const T rri = cx(i) == 0 ? k.rr0 : k.rr1;
+    const T rdy = cx(i) == 0 ? sel(cy(i), a0m, a00, a0p) : sel(cy(i), a1m, a10, a1p);
     P[i] = hx * hy;
-    // f_i^eq - w_i rho0 = drho Phi_x Phi_y + rho0 (d_x Phi_y + r_x d_y)
-    feqs[i] = drho * P[i] + (k.rho0 * dxi * hy + rri * dyi);
+    E[i] = sel(cx(i), rdxm, rdx0, rdxp) * hy + rdy;
   }
   if (rec) {
     rec[0] = rho;
@@ -133,71 +147,76 @@ __device__ __forceinline__ void collide(const T g[Q], T out[Q], const Coef<T>& k
 
   if (MODEL == M_BGK) {
 #pragma unroll
-    for (int i = 0; i < Q; ++i) out[i] = feqs[i] + k.omb * (g[i] - feqs[i]);
+    for (int i = 0; i < Q; ++i) {
+      const T feqs = drho * P[i] + E[i];
+      out[i] = feqs + k.omb * (g[i] - feqs);
+    }
     if (rec) rec[3] = rec[4] = T(0);
     return;
   }
 
   // Traceless non-equilibrium stress (inner sum of eq:oreg): N_xx = (D - rho(ux^2 - uy^2))/2,
   // N_xy = Pxy - rho ux uy.
-  const T Dm = (g[1] + g[3]) - (g[2] + g[4]);
-  const T Pxy = (g[5] + g[7]) - (g[6] + g[8]);
-  const T Nxx = T(0.5) * (Dm - rho * (ux2 - uy2));
+  const T Dm = s13 - s24;
+  const T Pxy = s57 - s68;
+  const T du2 = ux2 - uy2;
+  const T Nxx = T(0.5) * (Dm - rho * du2);
   const T Nxy = Pxy - jx * uy;
   if (rec) {
     rec[3] = Nxx;
     rec[4] = Nxy;
   }
-  // f_i^OReg = Phi_x Phi_y [(Cx^2 - Cy^2) N_xx + 2 Cx Cy N_xy] / (2 theta^2), C = c - u (eq:oreg).
-  // Everything downstream (psi, the prefactor, Pi~, Psi) is linear in f^OReg, so the
-  // relaxation factor 1 - 1/tau is folded into N here: fo, psi, pf, Pi~ and Psi below are
-  // all (1 - 1/tau) times the paper's quantities.
+  // f_i^OReg = P_i t_i, t_i = [(Cx^2 - Cy^2) N_xx + 2 Cx Cy N_xy] / (2 theta^2), C = c - u
+  // (eq:oreg). Everything downstream (psi, the prefactor, Pi~, Psi) is linear in f^OReg, so
+  // the relaxation factor 1 - 1/tau is folded into N here: t, psi, pf, Pi~ and Psi below are
+  // all (1 - 1/tau) times the paper's quantities. drho is folded into the x-factor so that
+  // P_i (drho + t_i) is one product.
   const T n1 = Nxx * k.omb_inv2th2, n2 = Nxy * (T(2) * k.omb_inv2th2);
   const T Cxm = T(-1) - ux, Cx0 = -ux, Cxp = T(1) - ux;
   const T Cym = T(-1) - uy, Cy0 = -uy, Cyp = T(1) - uy;
-  const T X1m = Cxm * Cxm * n1, X10 = Cx0 * Cx0 * n1, X1p = Cxp * Cxp * n1;
-  const T Y1m = Cym * Cym * n1, Y10 = Cy0 * Cy0 * n1, Y1p = Cyp * Cyp * n1;
+  const T X1m = Cxm * Cxm * n1 + drho, X10 = ux2 * n1 + drho, X1p = Cxp * Cxp * n1 + drho;
+  const T Y1m = Cym * Cym * n1, Y10 = uy2 * n1, Y1p = Cyp * Cyp * n1;
   const T Y2m = Cym * n2, Y20 = Cy0 * n2, Y2p = Cyp * n2;
-  T fo[Q];
-#pragma unroll
-  for (int i = 0; i < Q; ++i) {
-    const T t = sel(cx(i), X1m, X10, X1p) - sel(cy(i), Y1m, Y10, Y1p) +
-                sel(cx(i), Cxm, Cx0, Cxp) * sel(cy(i), Y2m, Y20, Y2p);
-    fo[i] = P[i] * t;
-  }
 
   T Psi[Q];
 #pragma unroll
   for (int i = 0; i < Q; ++i) Psi[i] = T(0);
   if (MODEL == M_PARTIAL || MODEL == M_COMPLETE) {
-    // psi = sum_i c_i f_i^OReg (eq:oreg-mom-compatibility, direct moment).
-    const T psx = (fo[1] - fo[3]) + (fo[5] - fo[6]) + (fo[8] - fo[7]);
-    const T psy = (fo[2] - fo[4]) + (fo[5] - fo[7]) + (fo[6] - fo[8]);
+    // psi = sum_i c_i f_i^OReg (eq:oreg-mom-compatibility) in closed form:
+    // psi_x = n1 u_x (1 - 3 theta - u_x^2), psi_y = -n1 u_y (1 - 3 theta - u_y^2).
+    // Every Psi_i takes half of a psi or Pi~ component, so halves are formed directly.
+    const T hpsx = n1 * hux * (k.c3 - ux2);
+    const T hpsy = -(n1 * huy * (k.c3 - uy2));
     if (MODEL == M_PARTIAL) {
       // eq:partial-corrections
-      Psi[1] = T(-0.5) * psx;
-      Psi[3] = T(0.5) * psx;
-      Psi[2] = T(-0.5) * psy;
-      Psi[4] = T(0.5) * psy;
+      Psi[1] = -hpsx;
+      Psi[3] = hpsx;
+      Psi[2] = -hpsy;
+      Psi[4] = hpsy;
     } else {
-      // Prefactor (eq:geq-prefactor-evaluation) and stress error (three cases).
-      const T pf = -k.inv4th2 * ((fo[1] + fo[3]) - (fo[2] + fo[4]));
-      const T ax = k.a0 + ux2 * (ux2 - T(1));
-      const T ay = k.a0 + uy2 * (uy2 - T(1));
-      const T Ptxx = -pf * ax, Ptyy = pf * ay, Ptxy = pf * (ux * uy * (ux2 - uy2));
+      // Prefactor (eq:geq-prefactor-evaluation), pf = -(1/(4 theta^2)) sum (cx^2 - cy^2) f^OReg
+      // with sum (cx^2 - cy^2) f^OReg = n1 (2 theta (1 - theta) + e_x + e_y),
+      // e = u^2 (u^2 - 1), and the stress error's three cases (halved).
+      const T exx = ux2 * (ux2 - T(1)), eyy = uy2 * (uy2 - T(1));
+      const T hpf = -k.inv8th2 * (n1 * (k.b0 + (exx + eyy)));
+      const T hPtxx = -hpf * (k.a0 + exx), hPtyy = hpf * (k.a0 + eyy), hPtxy = hpf * (ux * uy * du2);
       // eq:complete-corrections
-      Psi[1] = T(0.5) * (Ptyy - psx);
-      Psi[3] = T(0.5) * (Ptyy + psx);
-      Psi[2] = T(0.5) * (Ptxx - psy);
-      Psi[4] = T(0.5) * (Ptxx + psy);
-      const T s = T(-0.25) * (Ptxx + Ptyy);
-      Psi[5] = Psi[7] = s - T(0.25) * Ptxy;
-      Psi[6] = Psi[8] = s + T(0.25) * Ptxy;
+      Psi[1] = hPtyy - hpsx;
+      Psi[3] = hPtyy + hpsx;
+      Psi[2] = hPtxx - hpsy;
+      Psi[4] = hPtxx + hpsy;
+      const T s = T(-0.5) * (hPtxx + hPtyy);
+      Psi[5] = Psi[7] = s - T(0.5) * hPtxy;
+      Psi[6] = Psi[8] = s + T(0.5) * hPtxy;
     }
   }
-  // g*_i = (f_i^eq - w_i rho0) + (1 - 1/tau)(f_i^OReg + Psi_i)
+  // g*_i = (f_i^eq - w_i rho0) + (1 - 1/tau)(f_i^OReg + Psi_i) = P_i (drho + t_i) + E_i + Psi_i
 #pragma unroll
-  for (int i = 0; i < Q; ++i) out[i] = feqs[i] + (fo[i] + Psi[i]);
+  for (int i = 0; i < Q; ++i) {
+    const T u = sel(cx(i), X1m, X10, X1p) - sel(cy(i), Y1m, Y10, Y1p) +
+                sel(cx(i), Cxm, Cx0, Cxp) * sel(cy(i), Y2m, Y20, Y2p);
+    out[i] = P[i] * u + (E[i] + Psi[i]);
+  }
 }
 
 // ---------------------------------------------------------------------------------------

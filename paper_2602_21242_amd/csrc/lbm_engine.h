@@ -75,12 +75,10 @@ inline Coef<T> make_coef(const RunDesc& d) {
   k.rr1 = T(d.rho0 * double(k.r1));
   k.inv2th2 = T(1.0 / (2.0 * th * th));
   k.inv4th2 = T(1.0 / (4.0 * th * th));
+  k.inv8th2 = T(1.0 / (8.0 * th * th));
   k.a0 = T(th * (1.0 - 3.0 * th));
-  for (int i = 0; i < Q; ++i) {
-    const double rx = cx(i) == 0 ? 1.0 - th : 0.5 * th;
-    const double ry = cy(i) == 0 ? 1.0 - th : 0.5 * th;
-    k.wr[i] = T(rx * ry * d.rho0);
-  }
+  k.b0 = T(2.0 * th * (1.0 - th));
+  k.c3 = T(1.0 - 3.0 * th);
   return k;
 }
 

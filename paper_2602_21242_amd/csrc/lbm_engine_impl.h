@@ -12,14 +12,15 @@ namespace lbm {
 
 __host__ __device__ __forceinline__ int row_pos(int x, int S) { return (x % S) * kLanes + x / S; }
 
-inline Geo make_geo(const RunDesc& d) {
+inline Geo make_geo(const RunDesc& d, int npt) {
   Geo g;
   g.nx = d.nx;
   g.ny = d.ny;
   g.S = d.pitch / kLanes;
   g.ps = d.pitch;
   g.rs = d.rs;
-  g.nseg = (d.pitch + kBlock - 1) / kBlock;
+  const int groups_per_block = (kBlock / kLanes) * npt;
+  g.nseg = (g.S + groups_per_block - 1) / groups_per_block;
   g.plast = row_pos(d.nx - 1, g.S);
   return g;
 }
@@ -273,25 +274,45 @@ k_ic_adjoint(const S* buf0, RunDesc d, LayoutSel L, const T* fbar, T* uxb, T* uy
 
 // --- step dispatch ---------------------------------------------------------------------------
 
-template <class S, int MODEL>
-hipError_t launch_step_m(const RunDesc& d, int phase, const void* src, void* dst, void* rec, hipStream_t st) {
+template <class S, int MODEL, int NPT>
+hipError_t launch_step_n(const RunDesc& d, int phase, const void* src, void* dst, void* rec, hipStream_t st) {
   using T = typename StorageTraits<S>::T;
-  const Geo g = make_geo(d);
+  const Geo g = make_geo(d, NPT);
   const Coef<T> k = make_coef<T>(d);
   const S* s = static_cast<const S*>(src);
   S* o = static_cast<S*>(dst);
   T* r = static_cast<T*>(rec);
   const dim3 grid = step_grid(g), block(kBlock);
   if (rec) {
-    if (phase == PH_AB) hipLaunchKernelGGL((k_step<S, MODEL, PH_AB, true>), grid, block, 0, st, s, o, g, k, r, d.rs_rec);
-    else if (phase == PH_AA_EVEN) hipLaunchKernelGGL((k_step<S, MODEL, PH_AA_EVEN, true>), grid, block, 0, st, s, o, g, k, r, d.rs_rec);
-    else hipLaunchKernelGGL((k_step<S, MODEL, PH_AA_ODD, true>), grid, block, 0, st, s, o, g, k, r, d.rs_rec);
+    if (phase == PH_AB) hipLaunchKernelGGL((k_step<S, MODEL, PH_AB, true, NPT>), grid, block, 0, st, s, o, g, k, r, d.rs_rec);
+    else if (phase == PH_AA_EVEN) hipLaunchKernelGGL((k_step<S, MODEL, PH_AA_EVEN, true, NPT>), grid, block, 0, st, s, o, g, k, r, d.rs_rec);
+    else hipLaunchKernelGGL((k_step<S, MODEL, PH_AA_ODD, true, NPT>), grid, block, 0, st, s, o, g, k, r, d.rs_rec);
   } else {
-    if (phase == PH_AB) hipLaunchKernelGGL((k_step<S, MODEL, PH_AB, false>), grid, block, 0, st, s, o, g, k, r, d.rs_rec);
-    else if (phase == PH_AA_EVEN) hipLaunchKernelGGL((k_step<S, MODEL, PH_AA_EVEN, false>), grid, block, 0, st, s, o, g, k, r, d.rs_rec);
-    else hipLaunchKernelGGL((k_step<S, MODEL, PH_AA_ODD, false>), grid, block, 0, st, s, o, g, k, r, d.rs_rec);
+    if (phase == PH_AB) hipLaunchKernelGGL((k_step<S, MODEL, PH_AB, false, NPT>), grid, block, 0, st, s, o, g, k, r, d.rs_rec);
+    else if (phase == PH_AA_EVEN) hipLaunchKernelGGL((k_step<S, MODEL, PH_AA_EVEN, false, NPT>), grid, block, 0, st, s, o, g, k, r, d.rs_rec);
+    else hipLaunchKernelGGL((k_step<S, MODEL, PH_AA_ODD, false, NPT>), grid, block, 0, st, s, o, g, k, r, d.rs_rec);
   }
   return hipGetLastError();
+}
+
+// Nodes per thread of the step kernel. Two or four nodes per thread put more loads in flight
+// before the first collision, which pays where the collision is long relative to the bytes
+// moved (16-bit storage); the FP32 and FP64 paths are bandwidth-bound and run fastest with one.
+// Measured on MI355X, 8192^2, complete model (GLUPS, 1/2/4 nodes per thread): FP16
+// 148/160/167, BF16 149/168/168, FP32 90.6/82.6/81.0; LBGK FP16 176/178/168.
+template <class S> struct NodesPerThread { static constexpr int oreg = 1, bgk = 1; };
+template <> struct NodesPerThread<_Float16> { static constexpr int oreg = 4, bgk = 2; };
+template <> struct NodesPerThread<bf16_t> { static constexpr int oreg = 2, bgk = 2; };
+
+template <class S, int MODEL>
+hipError_t launch_step_m(const RunDesc& d, int phase, const void* src, void* dst, void* rec, hipStream_t st) {
+  constexpr int npt = MODEL == M_BGK ? NodesPerThread<S>::bgk : NodesPerThread<S>::oreg;
+  // A wavefront's NPT groups must all lie inside the row or all past it.
+  if constexpr (npt > 1) {
+    if ((d.pitch / kLanes) % (npt * kBlock / kLanes) == 0)
+      return launch_step_n<S, MODEL, npt>(d, phase, src, dst, rec, st);
+  }
+  return launch_step_n<S, MODEL, 1>(d, phase, src, dst, rec, st);
 }
 
 template <class S>
@@ -374,7 +395,7 @@ hipError_t Engine<S>::fbar_export(const RunDesc& d, const T* fbar, T* dense, hip
 
 template <class S>
 hipError_t Engine<S>::adjoint_step(const RunDesc& d, const T* fbar_next, T* fbar, const T* rec, hipStream_t st) {
-  const Geo g = make_geo(d);
+  const Geo g = make_geo(d, 1);
   const Coef<T> k = make_coef<T>(d);
   const dim3 grid = step_grid(g), block(kBlock);
   switch (d.model) {

@@ -14,9 +14,10 @@
 // window. Loads and stores are nontemporal: every population is read once and written once
 // per step. Padding positions (x >= nx, last lanes only) are never read or written.
 //
-// One thread updates one node; a block of 256 threads covers four groups of one row, so the
-// row, its two periodic neighbours and every row/population base address are uniform
-// (scalar registers) and each lane only adds its 32-bit in-row offset.
+// One thread updates NPT nodes (one lane of NPT consecutive groups); a block of 256 threads
+// covers 4 NPT groups of one row, so the row, its two periodic neighbours and every
+// row/population base address are uniform (scalar registers) and each lane only adds its
+// 32-bit in-row offset.
 //
 // Streaming patterns. The state at time n satisfies f_i^n(x) = buf[s(i)][x - d c_i]:
 //   A-B:       d = 1, s(i) = i (the buffer holds post-collision values at their origin;
@@ -42,7 +43,7 @@ struct Geo {
   int S;           // groups per row (pitch / 64)
   int ps;          // elements between the rows of two populations of one lattice row
   int64_t rs;      // elements between two lattice rows
-  int nseg;        // blocks per lattice row = ceil(pitch / kBlock)
+  int nseg;        // blocks per lattice row = ceil(S / (4 NPT))
   int plast;       // pos(nx - 1)
 };
 
@@ -93,33 +94,53 @@ struct RowPos {
   __device__ __forceinline__ int of() const { return DX == 0 ? p0 : (DX < 0 ? pm : pp); }
 };
 
-// Block -> lattice row (uniform), thread -> in-row position q and its node. Grid:
-// (nseg, min(ny, kRowsY), ceil(ny / kRowsY)). Returns false for positions past the row
-// and for padding.
-__device__ __forceinline__ bool map_thread(const Geo& geo, int& y, RowPos& r) {
-  y = int(blockIdx.z) * kRowsY + int(blockIdx.y);
-  const int q = int(blockIdx.x) * kBlock + int(threadIdx.x);
-  const int s = q / kLanes, lane = q % kLanes;
+// In-row positions of the node in group s at lane `lane` and of its periodic x-neighbours;
+// false past the row (s >= S) and for padding.
+__device__ __forceinline__ bool node_pos(const Geo& geo, int s, int lane, RowPos& r) {
+  const int q = s * kLanes + lane;
   const int x = lane * geo.S + s;
-  if (y >= geo.ny || s >= geo.S || x >= geo.nx) return false;
+  if (s >= geo.S || x >= geo.nx) return false;
   r.p0 = q;
   r.pm = s > 0 ? q - kLanes : (lane > 0 ? (geo.S - 1) * kLanes + lane - 1 : geo.plast);
   r.pp = x + 1 == geo.nx ? 0 : (s + 1 < geo.S ? q + kLanes : lane + 1);
   return true;
 }
 
-// One time step for one node per thread. src and dst alias in the AA phases. With REC the
-// moments (rho, u_x, u_y, N_xx, N_xy) of every node are written to rec, laid out like the
-// populations with five entries per lattice row (row stride rec_rs).
-template <class S, int MODEL, int PH, bool REC>
+// Block -> lattice row (uniform); the block's wavefronts take NPT consecutive groups each,
+// starting at the returned group s0. Grid: (nseg, min(ny, kRowsY), ceil(ny / kRowsY)) with
+// nseg = ceil(S / (4 NPT)). A block is four 64-lane wavefronts, so s0 is uniform across a
+// wavefront and is kept in a scalar register.
+static_assert(kBlock % kLanes == 0, "a block must consist of whole 64-node groups");
+template <int NPT>
+__device__ __forceinline__ int first_group(int& y, int& lane) {
+  y = int(blockIdx.z) * kRowsY + int(blockIdx.y);
+  lane = int(threadIdx.x % kLanes);
+  return (int(blockIdx.x) * (kBlock / kLanes) + __builtin_amdgcn_readfirstlane(int(threadIdx.x / kLanes))) * NPT;
+}
+
+// One time step; each thread updates NPT nodes (same lane, consecutive groups), issuing the
+// loads of all of them before the first collision so that more memory traffic is in flight
+// per wavefront. src and dst alias in the AA phases. With REC the moments (rho, u_x, u_y,
+// N_xx, N_xy) of every node are written to rec, laid out like the populations with five
+// entries per lattice row (row stride rec_rs).
+template <class S, int MODEL, int PH, bool REC, int NPT>
 __global__ void __launch_bounds__(kBlock)
 k_step(const S* src, S* dst, Geo geo, Coef<typename StorageTraits<S>::T> k,
        typename StorageTraits<S>::T* rec, int64_t rec_rs) {
   using T = typename StorageTraits<S>::T;
   using Tr = StorageTraits<S>;
-  int y;
-  RowPos rp;
-  if (!map_thread(geo, y, rp)) return;
+  int y, lane;
+  const int s0 = first_group<NPT>(y, lane);
+  // Uniform exits only: the host launches NPT > 1 only when S is a multiple of 4 NPT, so a
+  // wavefront's groups are either all inside the row or all past it. Padding lanes
+  // (x >= nx) run on their own padding slot for every access (no real node reads those
+  // slots and each still has one reader and one writer), so that all loads of the thread
+  // stay in one basic block and are issued back to back.
+  if (y >= geo.ny || s0 >= geo.S) return;
+  RowPos rp[NPT];
+#pragma unroll
+  for (int n = 0; n < NPT; ++n)
+    if (!node_pos(geo, s0 + n, lane, rp[n])) rp[n].p0 = rp[n].pm = rp[n].pp = (s0 + n) * kLanes + lane;
   const int ym = (y == 0) ? geo.ny - 1 : y - 1;
   const int yp = (y == geo.ny - 1) ? 0 : y + 1;
   const size_t rsb = size_t(geo.rs) * sizeof(S), psb = size_t(geo.ps) * sizeof(S);
@@ -128,32 +149,39 @@ k_step(const S* src, S* dst, Geo geo, Coef<typename StorageTraits<S>::T> k,
   char* dr[3] = {reinterpret_cast<char*>(dst) + ym * rsb, reinterpret_cast<char*>(dst) + y * rsb,
                  reinterpret_cast<char*>(dst) + yp * rsb};
 
-  T g[Q];
-  static_for<0, Q>([&](auto I) {
-    constexpr int i = decltype(I)::value;
-    constexpr bool shift = (PH != PH_AA_EVEN);
-    constexpr int slot = (PH == PH_AA_ODD) ? opp(i) : i;
-    constexpr int dx = shift ? -cx(i) : 0;
-    constexpr int dy = shift ? -cy(i) : 0;
-    g[i] = Tr::load(ld1(at<S>(sr[dy + 1] + slot * psb, rp.of<dx>())));
-  });
-
-  T out[Q], rv[NREC];
-  collide<T, MODEL>(g, out, k, REC ? rv : nullptr);
-  if constexpr (REC) {
-    char* rrow = reinterpret_cast<char*>(rec) + y * (size_t(rec_rs) * sizeof(T));
+  S gs[NPT][Q];
 #pragma unroll
-    for (int r = 0; r < NREC; ++r) st1(at<T>(rrow + r * size_t(geo.ps) * sizeof(T), rp.p0), rv[r]);
+  for (int n = 0; n < NPT; ++n) {
+    static_for<0, Q>([&](auto I) {
+      constexpr int i = decltype(I)::value;
+      constexpr bool shift = (PH != PH_AA_EVEN);
+      constexpr int slot = (PH == PH_AA_ODD) ? opp(i) : i;
+      constexpr int dx = shift ? -cx(i) : 0;
+      constexpr int dy = shift ? -cy(i) : 0;
+      gs[n][i] = ld1(at<S>(sr[dy + 1] + slot * psb, rp[n].template of<dx>()));
+    });
   }
 
-  static_for<0, Q>([&](auto I) {
-    constexpr int i = decltype(I)::value;
-    constexpr bool shift = (PH == PH_AA_ODD);
-    constexpr int slot = (PH == PH_AA_EVEN) ? opp(i) : i;
-    constexpr int dx = shift ? cx(i) : 0;
-    constexpr int dy = shift ? cy(i) : 0;
-    st1(at<S>(dr[dy + 1] + slot * psb, rp.of<dx>()), Tr::store(out[i]));
-  });
+#pragma unroll
+  for (int n = 0; n < NPT; ++n) {
+    T g[Q], out[Q], rv[NREC];
+#pragma unroll
+    for (int i = 0; i < Q; ++i) g[i] = Tr::load(gs[n][i]);
+    collide<T, MODEL>(g, out, k, REC ? rv : nullptr);
+    if constexpr (REC) {
+      char* rrow = reinterpret_cast<char*>(rec) + y * (size_t(rec_rs) * sizeof(T));
+#pragma unroll
+      for (int r = 0; r < NREC; ++r) st1(at<T>(rrow + r * size_t(geo.ps) * sizeof(T), rp[n].p0), rv[r]);
+    }
+    static_for<0, Q>([&](auto I) {
+      constexpr int i = decltype(I)::value;
+      constexpr bool shift = (PH == PH_AA_ODD);
+      constexpr int slot = (PH == PH_AA_EVEN) ? opp(i) : i;
+      constexpr int dx = shift ? cx(i) : 0;
+      constexpr int dy = shift ? cy(i) : 0;
+      st1(at<S>(dr[dy + 1] + slot * psb, rp[n].template of<dx>()), Tr::store(out[i]));
+    });
+  }
 }
 
 // One reverse step of the discrete adjoint: fbar^n(x) = J(m^n(x))^T fbar*(x) with the
@@ -163,9 +191,10 @@ template <class T, int MODEL>
 __global__ void __launch_bounds__(kBlock)
 k_adjoint_step(const T* __restrict__ fbar_next, T* __restrict__ fbar, Geo geo, Coef<T> k,
                const T* __restrict__ rec, int64_t rec_rs) {
-  int y;
+  int y, lane;
+  const int s0 = first_group<1>(y, lane);
   RowPos rp;
-  if (!map_thread(geo, y, rp)) return;
+  if (y >= geo.ny || !node_pos(geo, s0, lane, rp)) return;
   const int ym = (y == 0) ? geo.ny - 1 : y - 1;
   const int yp = (y == geo.ny - 1) ? 0 : y + 1;
   const size_t rsb = size_t(geo.rs) * sizeof(T), psb = size_t(geo.ps) * sizeof(T);

@@ -82,6 +82,22 @@ def test_taylor_green_theta03_fp32(model, steps, pattern):
     assert e <= TOL["f32"]
 
 
+@pytest.mark.parametrize("storage,model", [("f16", "complete"), ("f16", "bgk"), ("bf16", "complete"),
+                                           ("f32", "complete"), ("f64", "partial")])
+@pytest.mark.parametrize("pattern", ["ab", "aa"])
+def test_ragged_rows_with_several_nodes_per_thread(storage, model, pattern):
+    """nx = 1000: 16 groups of 64 per row, the last 24 positions of each row padding. The
+    16-bit paths take two or four nodes per thread here, with padding lanes inside the
+    wavefronts; 1-3 steps from random populations against the oracle."""
+    nx, ny, th, nu = 1000, 6, 0.4, 0.02
+    f0 = inp.random_populations(nx, ny, seed=17, amp=0.02)
+    for n in (1, 2, 3):
+        sim = gpu_sim(nx, ny, th, nu, model, storage, pattern, f0=f0)
+        sim.step(n)
+        e = eps_f(sim.populations().cpu().numpy(), oracle.run(f0, th, nu, model, n))
+        assert e <= {"f64": 1e-13, "f32": 1e-6}.get(storage, TOL[storage]), (n, e)
+
+
 @pytest.mark.parametrize("theta", [1 / 3, 0.3, 0.55, 0.7])
 @pytest.mark.parametrize("model", ["bgk", "complete"])
 def test_uniform_flow_stays_fixed_fp32(model, theta):
