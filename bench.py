@@ -99,21 +99,37 @@ def copy_bandwidth(nbytes=2 << 30, reps=20):
 
 def cpu_baseline(w, model, budget_s=15.0):
     """The FP64 CPU oracle on the same workload (full grid), timed for a bounded number of
-    steps on the host cores."""
+    steps on all host cores; plus every model for 2 warm-up + 10 timed steps, and the
+    chosen model on one thread for one step (MLUPS)."""
     import oracle
     rho, ux, uy = w.fields(seed=0)
-    f = oracle.init_equilibrium(rho, ux, uy, w.theta)
+    f0 = oracle.init_equilibrium(rho, ux, uy, w.theta)
+    nodes = w.nx * w.ny
     t0 = time.perf_counter()
-    f = oracle.run(f, w.theta, w.nu, model, 1)
+    f = oracle.run(f0, w.theta, w.nu, model, 1)
     one = time.perf_counter() - t0
     n = max(1, min(50, int(budget_s / max(one, 1e-6))))
     t0 = time.perf_counter()
     oracle.run(f, w.theta, w.nu, model, n)
     dt = time.perf_counter() - t0
-    glups = w.nx * w.ny * n / dt / 1e9
-    return {"value": glups, "unit": "GLUPS", "cores": oracle.num_threads(), "kind": "oracle",
+    cores = oracle.num_threads()
+    per_model = {}
+    for m in ("bgk", "uc", "partial", "complete"):
+        g = oracle.run(f0, w.theta, w.nu, m, 2)
+        t0 = time.perf_counter()
+        oracle.run(g, w.theta, w.nu, m, 10)
+        per_model[m] = nodes * 10 / (time.perf_counter() - t0) / 1e6
+    oracle.set_num_threads(1)
+    try:
+        t0 = time.perf_counter()
+        oracle.run(f0, w.theta, w.nu, model, 1)
+        single = nodes / (time.perf_counter() - t0) / 1e6
+    finally:
+        oracle.set_num_threads(cores)
+    return {"value": nodes * n / dt / 1e9, "unit": "GLUPS", "cores": cores, "kind": "oracle",
             "sample": f"{w.name} {w.nx}x{w.ny} {model} model, {n} steps after 1 warm-up step, "
-                      f"{dt:.1f} s, host cpu_count={os.cpu_count()}"}
+                      f"{dt:.1f} s, host cpu_count={os.cpu_count()}",
+            "mlups_per_model": per_model, "mlups_single_thread": single}
 
 
 def main():
@@ -129,9 +145,11 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--precision-steps", type=int, default=1000,
                     help="steps of the 8192^2 storage-precision comparison")
-    ap.add_argument("--only", choices=["adjoint", "precision"], default=None,
+    ap.add_argument("--only", choices=["adjoint", "precision", "viscosity", "shear-layer"], default=None,
                     help="run only one section and print its JSON (adjoint: sweep and end-to-end gradient; "
-                         "precision: storage types on the 8192^2 turbulence workload against the FP64 run)")
+                         "precision: storage types on the 8192^2 turbulence workload against the FP64 run; "
+                         "viscosity: rotated shear-wave nu~/nu over theta, Mach number and model; "
+                         "shear-layer: the double shear layer at the paper's parameters over n, theta and model)")
     ap.add_argument("--copy-probe", type=int, default=0,
                     help="only run a device-to-device copy of this many bytes (counter scaling)")
     args = ap.parse_args()
@@ -162,6 +180,12 @@ def main():
         return
     if args.only == "precision":
         print(json.dumps(bench_precision(inp)), flush=True)
+        return
+    if args.only == "viscosity":
+        print(json.dumps(bench_viscosity()), flush=True)
+        return
+    if args.only == "shear-layer":
+        print(json.dumps(bench_shear_layer()), flush=True)
         return
 
     w = inp.WORKLOADS[args.workload]
@@ -244,9 +268,23 @@ def main():
     print(json.dumps(out), flush=True)
 
 
+def shell_spectrum(ux, uy):
+    """Kinetic-energy spectrum E(K) = 1/2 sum over |k| in [K - 1/2, K + 1/2) of |u_hat|^2 of a
+    square periodic field (FP64 FFT on the device; a diagnostic, not part of the step)."""
+    import torch
+    n = ux.shape[0]
+    fx = torch.fft.fft2(ux.double()) / ux.numel()
+    fy = torch.fft.fft2(uy.double()) / uy.numel()
+    e = 0.5 * (fx.abs() ** 2 + fy.abs() ** 2)
+    k = torch.fft.fftfreq(n, d=1.0 / n, device=ux.device, dtype=torch.float64)
+    K = torch.round(torch.sqrt(k[:, None] ** 2 + k[None, :] ** 2)).long()
+    return torch.bincount(K.flatten(), weights=e.flatten()).cpu()
+
+
 def bench_precision(inp, checkpoints=(100, 1000, 5000)):
     """Storage precision on the 8192^2 decaying-turbulence workload (complete model): errors
-    of FP32, FP16 and BF16 storage against the FP64-storage run at the given steps."""
+    of FP32, FP16 and BF16 storage against the FP64-storage run at the given steps
+    (populations, velocity, density, kinetic energy and the shell energy spectrum)."""
     import torch
     w = inp.WORKLOADS["turb8192"]
     fields = w.fields(seed=0)
@@ -259,7 +297,7 @@ def bench_precision(inp, checkpoints=(100, 1000, 5000)):
         done = n
         r, ux, uy = s.moments()
         ref[n] = dict(f=s.populations(dtype=torch.float32).cpu(), rho=r.cpu(), ux=ux.cpu(), uy=uy.cpu(),
-                      ke=float(0.5 * (r * (ux * ux + uy * uy)).sum()))
+                      ke=float(0.5 * (r * (ux * ux + uy * uy)).sum()), spec=shell_spectrum(ux, uy))
     del s
     out = {"workload": w.name, "model": "complete", "reference": "FP64 storage, FP64 arithmetic",
            "ke_reference": {str(n): ref[n]["ke"] for n in checkpoints}}
@@ -276,6 +314,9 @@ def bench_precision(inp, checkpoints=(100, 1000, 5000)):
             R = ref[n]
             ke = float(0.5 * (r * (ux * ux + uy * uy)).sum())
             umax = max(float(R["ux"].abs().max()), float(R["uy"].abs().max()))
+            spec = shell_spectrum(ux, uy)
+            nk = min(len(spec), len(R["spec"]))
+            rel = (spec[:nk] - R["spec"][:nk]).abs() / R["spec"][:nk]
             res[str(n)] = {
                 "eps_f": float((f.double() - R["f"].double()).abs().max() / R["f"].double().abs().max()),
                 "eps_u_inf": max(float((ux.cpu() - R["ux"]).abs().max()), float((uy.cpu() - R["uy"]).abs().max())) / umax,
@@ -283,10 +324,54 @@ def bench_precision(inp, checkpoints=(100, 1000, 5000)):
                                              / (R["ux"] ** 2 + R["uy"] ** 2).sum())),
                 "eps_rho": float((r.cpu() - R["rho"]).abs().max() / (R["rho"] - w.rho0).abs().max()),
                 "ke_rel": ke / R["ke"] - 1.0,
+                "spectrum_max_rel_K4_64": float(rel[4:65].max()),
+                "spectrum_rel_l1": float((spec[:nk] - R["spec"][:nk]).abs().sum() / R["spec"][:nk].sum()),
             }
         out[storage] = res
         del s
     return out
+
+
+def bench_viscosity(thetas=(0.25, 1.0 / 3.0, 0.4, 0.5), machs=tuple(i / 10 for i in range(11)),
+                    models=("bgk", "uc", "partial", "complete"), n=200, nu=1e-3, amp=1e-3, skip=200, steps=1000):
+    """Effective viscosity nu~/nu of the pi/4-rotated decaying shear wave (the paper's first
+    benchmark: nu = 1e-3, amplitude 1e-3, 1200 iterations; here a doubly periodic n x n box)
+    over theta, the Mach number U/sqrt(theta) of the advecting flow and the model; FP64
+    storage. null = the wave blew up or grew."""
+    from paper_2602_21242_amd.diagnostics import rotated_wave_viscosity
+    t0 = time.perf_counter()
+    table = {}
+    for th in thetas:
+        log(f"[viscosity] theta {th:.4f}")
+        table[f"{th:.4f}"] = {m: [rotated_wave_viscosity(m, th, nu, ma, n=n, A=amp, skip=skip, steps=steps)
+                                  for ma in machs] for m in models}
+    return {"workload": f"rotated shear wave {n}x{n}, nu={nu}, A={amp}, decay over steps {skip}..{skip + steps}, "
+                        f"FP64 storage", "mach": list(machs), "nu_ratio": table,
+            "seconds": time.perf_counter() - t0}
+
+
+def bench_shear_layer(grids=(128, 256, 512), thetas=(0.4, 0.6), models=("bgk", "uc", "partial", "complete"),
+                      extra=((0.6, 1024), (0.6, 2048))):
+    """The double shear layer at the paper's parameters (u0 = 0.04, kappa = 80, delta = 0.05,
+    Re = 30000, one convective time n/u0, FP64 storage): stability, vorticity thickness of
+    the x-averaged profile (box units; 2/kappa = 0.025 initially), vortex cores above 30 % of
+    the peak vorticity, per model, grid and theta; LBGK and the complete model also at the
+    larger grids for theta = 0.6."""
+    import torch
+    from paper_2602_21242_amd.diagnostics import double_shear_layer_run
+    t0 = time.perf_counter()
+    runs = []
+    cases = [(th, n, m) for th in thetas for n in grids for m in models]
+    cases += [(th, n, m) for th, n in extra for m in ("bgk", "complete")]
+    for th, n, m in cases:
+        log(f"[shear-layer] theta {th} n {n} {m}")
+        t1 = time.perf_counter()
+        r = double_shear_layer_run(m, th, n)
+        torch.cuda.synchronize()
+        r.update(theta=th, n=n, model=m, seconds=time.perf_counter() - t1)
+        runs.append(r)
+    return {"workload": "double shear layer, u0=0.04, kappa=80, delta=0.05, Re=30000, 1 convective time, FP64",
+            "runs": runs, "seconds": time.perf_counter() - t0}
 
 
 def bench_adjoint(inp):

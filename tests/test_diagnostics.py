@@ -1,0 +1,59 @@
+"""The package's flow diagnostics (torch, run here on CPU tensors) against closed forms:
+mode amplitude and decay viscosity, vorticity of a sine field, thickness of a tanh layer,
+vortex-core count of separated Gaussian vortices."""
+import math
+
+import pytest
+import torch
+
+from paper_2602_21242_amd import diagnostics as d
+
+
+def _grid(n):
+    x = torch.arange(n, dtype=torch.float64)[None, :]
+    y = torch.arange(n, dtype=torch.float64)[:, None]
+    return x, y
+
+
+def test_mode_amplitude_and_decay_viscosity():
+    n, A, U = 48, 1e-3, 0.1
+    x, y = _grid(n)
+    u = U / math.sqrt(2) + A * torch.sin(2 * math.pi * (-x + y) / n)
+    a = d.mode_amplitude(u, u.clone(), -1, 1)
+    # u_x + u_y = sqrt(2) U + 2 A sin(phi): the coefficient at +k is 2A/(2i) = -iA
+    assert abs(a - (-1j * A)) < 1e-15
+    k2 = 2 * (2 * math.pi / n) ** 2
+    assert d.decay_viscosity(a, a * math.exp(-0.01 * k2 * 300), k2, 300) == pytest.approx(0.01, rel=1e-12)
+
+
+def test_vorticity_of_sine_fields():
+    n = 64
+    x, y = _grid(n)
+    k = 2 * math.pi / n
+    ux = torch.sin(k * y) + 0 * x
+    uy = torch.sin(k * x) + 0 * y
+    # central differences of sin(k s) give sin(k) cos(k s)
+    w = d.vorticity(ux, uy)
+    ref = math.sin(k) * (torch.cos(k * x) - torch.cos(k * y))
+    assert float((w - ref).abs().max()) < 1e-14
+
+
+def test_thickness_of_tanh_layers():
+    n, u0, kappa = 1024, 0.04, 80.0
+    x, y = _grid(n)
+    s = y / n
+    ux = torch.where(y <= n / 2, u0 * torch.tanh(kappa * (s - 0.25)), u0 * torch.tanh(kappa * (0.75 - s))) + 0 * x
+    # vorticity thickness 2 u0 / max dU/dy; the steepest point y = n/4 is a grid node, where
+    # the central difference of u0 tanh(kappa (y/n - 1/4)) is u0 tanh(kappa/n) (2/kappa of the
+    # box height in the continuum limit)
+    assert d.shear_layer_thickness(ux, u0) == pytest.approx(2 / (n * math.tanh(kappa / n)), rel=1e-12)
+
+
+def test_vortex_cores_counts_separated_vortices_across_the_wrap():
+    n = 128
+    x, y = _grid(n)
+    wrap = lambda a: (a + n / 2) % n - n / 2
+    g = lambda cx, cy, s: torch.exp(-(wrap(x - cx) ** 2 + wrap(y - cy) ** 2) / (2 * s * s))
+    om = g(0, 0, 4) - g(64, 70, 5) + 0.1 * g(30, 100, 3)    # the weak one is below 30 %
+    assert d.vortex_cores(om) == 2
+    assert d.vortex_cores(om, frac=0.05) == 3
