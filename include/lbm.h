@@ -100,22 +100,24 @@ lbm_status lbm_init(const lbm_params* p, void* d_workspace, size_t workspace_byt
                     void* hip_stream, const double* d_rho, const double* d_ux,
                     const double* d_uy, lbm_ctx** out);
 
-/* Advance n >= 0 time steps (eq:lbe: collide, then stream). While the context records
- * (record_steps > 0), the state at every checkpoint time below record_steps is saved;
- * stepping past record_steps is allowed but disables lbm_adjoint. */
+/* Advance n >= 0 time steps (eq:lbe: collide, then stream); n = 0 does nothing and n < 0
+ * is LBM_ERR_INVALID_ARGUMENT. While the context records (record_steps > 0), the state at
+ * every checkpoint time below record_steps is saved; stepping past record_steps is allowed
+ * but disables lbm_adjoint. */
 lbm_status lbm_step(lbm_ctx* ctx, int64_t n);
 
 /* Density and velocity rho = sum_i f_i, u = sum_i c_i f_i / rho of the pre-collision
  * state f^n at the current time n, written to FP64 or FP32 [ny][nx] arrays
- * (out_dtype LBM_F64 or LBM_F32). Any output pointer may be NULL. */
+ * (out_dtype LBM_F64 or LBM_F32; the 16-bit types give LBM_ERR_UNSUPPORTED). Any output
+ * pointer may be NULL. */
 lbm_status lbm_moments(lbm_ctx* ctx, lbm_dtype out_dtype, void* d_rho, void* d_ux, void* d_uy);
 
 /* Unshifted pre-collision populations f^n as a dense [9][ny][nx] array of out_dtype
- * (LBM_F64 or LBM_F32). */
+ * (LBM_F64 or LBM_F32; the 16-bit types give LBM_ERR_UNSUPPORTED). d_f must not be NULL. */
 lbm_status lbm_get_populations(lbm_ctx* ctx, lbm_dtype out_dtype, void* d_f);
 
-/* Replace the state at the current time by the FP64 [9][ny][nx] populations d_f
- * (rounded to the storage type). Disables lbm_adjoint for the recorded run. */
+/* Replace the state at the current time by the FP64 [9][ny][nx] populations d_f (not
+ * NULL; rounded to the storage type). Disables lbm_adjoint for the recorded run. */
 lbm_status lbm_set_populations(lbm_ctx* ctx, const double* d_f);
 
 /* FP64 totals of the pre-collision state: out[0] = sum rho, out[1] = sum rho u_x,

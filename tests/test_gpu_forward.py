@@ -181,3 +181,31 @@ def test_moments_of_populations():
         np.testing.assert_allclose(ux, uxo, rtol=0, atol=1e-15)
         np.testing.assert_allclose(uy, uyo, rtol=0, atol=1e-15)
         assert sim.time == 3
+
+
+def test_degenerate_calls_on_a_live_context():
+    """Zero steps is a no-op; a negative count and a NULL population buffer are invalid, a
+    16-bit output type unsupported, all rejected before any work with the state untouched;
+    NULL moment outputs are skipped."""
+    import torch
+    from paper_2602_21242_amd import capi
+    nx, ny = 21, 10
+    f0 = inp.random_populations(nx, ny, seed=23)
+    sim = gpu_sim(nx, ny, 0.4, 0.02, "complete", "f32", "aa", f0=f0)
+    sim.step(3)
+    before = sim.populations().cpu().numpy()
+    assert capi.lbm_step(sim._ctx, 0) == capi.LBM_OK and sim.time == 3
+    assert capi.lbm_step(sim._ctx, -1) == capi.LBM_ERR_INVALID_ARGUMENT and sim.time == 3
+    out = torch.empty((ny, nx), dtype=torch.float32, device="cuda")
+    assert capi.lbm_moments(sim._ctx, capi.LBM_F16, out.data_ptr(), None, None) == capi.LBM_ERR_UNSUPPORTED
+    assert capi.lbm_moments(sim._ctx, capi.LBM_F32, None, None, None) == capi.LBM_OK
+    assert capi.lbm_get_populations(sim._ctx, capi.LBM_F64, None) == capi.LBM_ERR_INVALID_ARGUMENT
+    assert capi.lbm_get_populations(sim._ctx, capi.LBM_BF16, out.data_ptr()) == capi.LBM_ERR_UNSUPPORTED
+    assert capi.lbm_set_populations(sim._ctx, None) == capi.LBM_ERR_INVALID_ARGUMENT
+    torch.cuda.synchronize()
+    assert np.array_equal(sim.populations().cpu().numpy(), before)
+    # the state still advances exactly like an undisturbed run (odd AA phase next)
+    sim.step(1)
+    ref = gpu_sim(nx, ny, 0.4, 0.02, "complete", "f32", "aa", f0=f0)
+    ref.step(4)
+    assert np.array_equal(sim.populations().cpu().numpy(), ref.populations().cpu().numpy())
