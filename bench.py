@@ -16,6 +16,7 @@ import hashlib
 import json
 import math
 import os
+import re
 import sys
 import time
 
@@ -32,12 +33,21 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
+def _strip_comments(text):
+    """C++ source without // and /* */ comments, trailing blanks and empty lines."""
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    text = re.sub(r"//[^\n]*", "", text)
+    return "\n".join(line.rstrip() for line in text.splitlines() if line.strip())
+
+
 def kernel_source_hash():
+    """sha256 (first 16 hex digits) of the library sources under csrc/, comments and blank
+    lines removed, so that counters taken on the same code stay valid across comment edits."""
     h = hashlib.sha256()
     for p in sorted(glob.glob(os.path.join(ROOT, "paper_2602_21242_amd", "csrc", "*"))):
-        with open(p, "rb") as fh:
+        with open(p, encoding="utf-8") as fh:
             h.update(os.path.basename(p).encode())
-            h.update(fh.read())
+            h.update(_strip_comments(fh.read()).encode())
     return h.hexdigest()[:16]
 
 

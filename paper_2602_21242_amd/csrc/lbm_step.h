@@ -12,7 +12,9 @@
 // MI355X for the 9-in/9-out pull.) The nine population rows of a lattice row are contiguous,
 // which keeps the 18 concurrent read/write streams of a step within a compact address
 // window. Loads and stores are nontemporal: every population is read once and written once
-// per step. Padding positions (x >= nx, last lanes only) are never read or written.
+// per step. Rows are padded to whole groups; padding positions (x >= nx, last lanes only)
+// are never read by a real node. The step kernel lets a padding lane read and write its own
+// padding slot (no per-lane guards), the other kernels skip padding.
 //
 // One thread updates NPT nodes (one lane of NPT consecutive groups); a block of 256 threads
 // covers 4 NPT groups of one row, so the row, its two periodic neighbours and every

@@ -135,7 +135,8 @@ def test_reduced_precision_storage(storage, model):
 
 FULL = [
     ("tg4096", "complete", "f32", "ab"), ("tg4096", "bgk", "f32", "ab"), ("tg4096", "partial", "f32", "ab"),
-    ("tg4096", "complete", "f32", "aa"), ("turb8192", "complete", "f16", "aa"), ("turb8192", "complete", "bf16", "ab"),
+    ("tg4096", "complete", "f32", "aa"), ("turb8192", "complete", "f16", "aa"), ("turb8192", "complete", "f16", "ab"),
+    ("turb8192", "complete", "bf16", "ab"),
     ("turb8192", "complete", "f64", "ab"), ("dsl16384", "complete", "f32", "aa"),
 ]
 
