@@ -210,3 +210,33 @@ def test_degenerate_calls_on_a_live_context():
     ref = gpu_sim(nx, ny, 0.4, 0.02, "complete", "f32", "aa", f0=f0)
     ref.step(4)
     assert np.array_equal(sim.populations().cpu().numpy(), ref.populations().cpu().numpy())
+
+
+@pytest.mark.parametrize("storage", ["f64", "f32", "f16"])
+@pytest.mark.parametrize("pattern", ["ab", "aa"])
+def test_step_graph_replays_match_single_launches(storage, pattern):
+    """On launch-bound grids (up to 2^15 storage positions; here 64 x 20) lbm_step(n >= 64)
+    replays a recorded HIP graph of 64 steps.
+    Several replays, from both buffer/phase parities, interleaved with single steps, moment
+    readouts and synchronisations, each compared bit for bit with a run advanced one
+    lbm_step(1) call at a time (never a graph); then with the oracle."""
+    import torch
+    nx, ny, th, nu = 48, 20, 0.4, 0.02
+    fields = inp.taylor_green(nx, ny, 0.05, th, noise=1e-3, seed=4)
+    a = gpu_sim(nx, ny, th, nu, "complete", storage, pattern, fields=fields)
+    b = gpu_sim(nx, ny, th, nu, "complete", storage, pattern, fields=fields)
+    total = 0
+    for chunk, extra in ((64, 1), (128, 0), (64, 3), (192, 1)):
+        a.step(chunk)
+        a.moments()
+        torch.cuda.synchronize()
+        for _ in range(chunk):
+            b.step(1)
+        total += chunk
+        assert a.time == b.time == total
+        assert np.array_equal(a.populations().cpu().numpy(), b.populations().cpu().numpy()), (chunk, total)
+        a.step(extra)
+        b.step(extra)
+        total += extra
+    ref = oracle.run(oracle.init_equilibrium(*fields, th), th, nu, "complete", total)
+    assert eps_f(a.populations().cpu().numpy(), ref) <= {"f64": 1e-12, "f32": 1e-5, "f16": 1e-3}[storage]
