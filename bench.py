@@ -406,7 +406,7 @@ def bench_adjoint(inp):
     nodes = w.nx * w.ny
     res["adjoint/tg4096/complete/f32/sweep"] = {
         "steps": N, "ms_total": ms_sweep, "GLUPS_gradient_sweep": nodes * N / (ms_sweep * 1e-3) / 1e9,
-        "note": "reverse sweep = checkpoint restore + recorded recomputation + adjoint step per step"}
+        "note": "reverse sweep = recorded recomputation from each checkpoint + adjoint step per step"}
     del sim
     # End-to-end gradient of the final kinetic energy on the 1024^2 shear wave.
     from paper_2602_21242_amd import LBMFunction

@@ -236,6 +236,21 @@ lbm_status step_graph(lbm_ctx* c, hipGraphExec_t* out) {
   return LBM_OK;
 }
 
+// One step whose input is another buffer (a checkpoint slot), written to population buffer
+// 0, which then holds the state. Valid for A-B and out of place for both AA phases: every
+// node writes all nine of its output locations.
+lbm_status step_from(lbm_ctx* c, const void* src, void* rec) {
+  return dispatch(c->p.storage, [&](auto eng) -> lbm_status {
+    using E = decltype(eng);
+    const int ph = c->p.pattern == LBM_AB ? lbm::PH_AB : ((c->time & 1) ? lbm::PH_AA_ODD : lbm::PH_AA_EVEN);
+    const hipError_t e = E::step(c->d, ph, src, c->ws + c->plan.pop_off[0], rec, c->stream);
+    if (e != hipSuccess) return fail(LBM_ERR_HIP, std::string("step kernel launch: ") + hipGetErrorString(e));
+    c->cur = 0;
+    ++c->time;
+    return LBM_OK;
+  });
+}
+
 lbm_status restore(lbm_ctx* c, int64_t slot, int64_t t) {
   HIP_TRY(hipMemcpyAsync(c->ws + c->plan.pop_off[0], c->ckpt(slot), c->plan.pop_bytes, hipMemcpyDeviceToDevice, c->stream));
   c->cur = 0;
@@ -245,15 +260,17 @@ lbm_status restore(lbm_ctx* c, int64_t slot, int64_t t) {
 
 // Reverse sweep over the recorded run: on entry fbar(0) holds dJ/df^N; on exit fbar(*out_b)
 // holds dJ/df^0. Segment k (steps [k s, min((k+1) s, N))) is recomputed from its checkpoint
-// while recording moments, then traversed backwards with the adjoint kernel.
+// while recording moments (the first step reads the checkpoint slot directly, so no copy
+// restores it), then traversed backwards with the adjoint kernel.
 lbm_status sweep(lbm_ctx* c, int* out_b) {
   const int64_t N = c->p.record_steps, s = c->plan.stride;
   int b = 0;
   for (int64_t k = c->plan.nck - 1; k >= 0; --k) {
     const int64_t t0 = k * s, t1 = std::min(t0 + s, N);
-    lbm_status st = restore(c, k, t0);
+    c->time = t0;
+    lbm_status st = step_from(c, c->ckpt(k), c->rec_slot(0));
     if (st != LBM_OK) return st;
-    for (int64_t t = t0; t < t1; ++t) {
+    for (int64_t t = t0 + 1; t < t1; ++t) {
       st = do_step(c, c->rec_slot(t - t0));
       if (st != LBM_OK) return st;
     }
