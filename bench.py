@@ -90,6 +90,22 @@ def time_steps(sim, steps, warmup):
     return start.elapsed_time(stop) / steps
 
 
+def time_single_steps(sim, steps, warmup):
+    """Like time_steps, with one lbm_step(1) call per step (always the single-step kernel)."""
+    import torch
+    for _ in range(warmup):
+        sim.step(1)
+    torch.cuda.synchronize()
+    start = torch.cuda.Event(enable_timing=True)
+    stop = torch.cuda.Event(enable_timing=True)
+    start.record(sim.stream)
+    for _ in range(steps):
+        sim.step(1)
+    stop.record(sim.stream)
+    torch.cuda.synchronize()
+    return start.elapsed_time(stop) / steps
+
+
 def copy_bandwidth(nbytes=2 << 30, reps=20):
     import torch
     a = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
@@ -152,6 +168,8 @@ def main():
     ap.add_argument("--storage", default="f32")
     ap.add_argument("--pattern", default="ab")
     ap.add_argument("--quick", action="store_true", help="headline only: no variants, no CPU baseline")
+    ap.add_argument("--single-step", action="store_true",
+                    help="time the headline with one lbm_step(1) call per step (the single-step kernel)")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--precision-steps", type=int, default=1000,
                     help="steps of the 8192^2 storage-precision comparison")
@@ -204,13 +222,18 @@ def main():
         f"{args.warmup} warm-up + {args.steps} timed steps")
     fields = w.fields(seed=0)
     sim = make_sim(w, args.model, args.storage, args.pattern, fields)
-    ms = time_steps(sim, args.steps, args.warmup)
+    spl = 1 if args.single_step else sim.steps_per_launch
+    ms = (time_single_steps if args.single_step else time_steps)(sim, args.steps, args.warmup)
     inv = sim.invariants(allow_nonfinite=True)
     del sim
     glups = nodes / (ms * 1e-3) / 1e9
-    achieved = ALG_BYTES[args.storage] * nodes / (ms * 1e-3) / 1e9
-    log(f"[bench] {ms:.4f} ms/step, {glups:.2f} GLUPS, {achieved:.0f} GB/s algorithmic")
+    # Algorithmic bytes per launch: one read and one write of the nine populations of every
+    # node, whether the launch advances one step or two (the two-step kernel keeps the
+    # intermediate state in LDS).
+    achieved = ALG_BYTES[args.storage] * nodes / (spl * ms * 1e-3) / 1e9
+    log(f"[bench] {ms:.4f} ms/step ({spl} step(s) per launch), {glups:.2f} GLUPS, {achieved:.0f} GB/s algorithmic")
     traffic = load_traffic(w.name, args.model, args.storage, args.pattern)
+    kernel = (f"k_step2<{args.storage},{args.model}>" if spl == 2 else f"k_step<{args.storage},{args.model},{args.pattern}>")
 
     out = {
         "metric": METRIC, "value": glups, "unit": "GLUPS", "n_gpus": 1, "steps": args.steps,
@@ -221,9 +244,9 @@ def main():
                    "initial_field": "Taylor-Green U0=0.1 + N(0,1e-3^2) velocity noise, seed 0"
                    if w.name == "tg4096" else w.extra},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
-                     "kernel": f"k_step<{args.storage},{args.model},{args.pattern}>",
-                     "alg_bytes_per_node": ALG_BYTES[args.storage]},
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic, "kernel": kernel,
+                     "steps_per_launch": spl, "alg_bytes_per_node_per_launch": ALG_BYTES[args.storage],
+                     "launch_us": spl * ms * 1e3},
         "mass_after_run": inv[0] if inv else None,
     }
 
@@ -236,10 +259,20 @@ def main():
                                ("uc", "aa"), ("partial", "aa")):
             log(f"[bench] variant tg4096 {model} f32 {pattern}")
             s = make_sim(w, model, "f32", pattern, fields)
+            sp = s.steps_per_launch
             m = time_steps(s, steps_v, 20)
             var[f"tg4096/{model}/f32/{pattern}"] = {"ms_per_step": m, "GLUPS": nodes / (m * 1e-3) / 1e9,
-                                                    "hbm_frac": 72 * nodes / (m * 1e-3) / 1e9 / HBM_PEAK_GBS}
+                                                    "steps_per_launch": sp,
+                                                    "hbm_frac": 72 * nodes / (sp * m * 1e-3) / 1e9 / HBM_PEAK_GBS}
             del s
+        # The single-step kernel on the headline workload (one lbm_step(1) call per step).
+        log("[bench] variant tg4096 complete f32 ab, one step per launch")
+        s = make_sim(w, "complete", "f32", "ab", fields)
+        m = time_single_steps(s, steps_v, 20)
+        var["tg4096/complete/f32/ab/single-step-kernel"] = {
+            "ms_per_step": m, "GLUPS": nodes / (m * 1e-3) / 1e9, "steps_per_launch": 1,
+            "hbm_frac": 72 * nodes / (m * 1e-3) / 1e9 / HBM_PEAK_GBS}
+        del s
         del fields
         # Storage types on the 8192^2 turbulence workload, with the error against the FP64 run.
         wt = inp.WORKLOADS["turb8192"]
@@ -250,9 +283,10 @@ def main():
         for storage in ("f64", "f32", "f16", "bf16"):
             log(f"[bench] variant turb8192 complete {storage} ab")
             s = make_sim(wt, "complete", storage, "ab", tf)
+            sp = s.steps_per_launch
             m = time_steps(s, 200, 20)
-            ent = {"ms_per_step": m, "GLUPS": nt / (m * 1e-3) / 1e9,
-                   "hbm_frac": ALG_BYTES[storage] * nt / (m * 1e-3) / 1e9 / HBM_PEAK_GBS}
+            ent = {"ms_per_step": m, "GLUPS": nt / (m * 1e-3) / 1e9, "steps_per_launch": sp,
+                   "hbm_frac": ALG_BYTES[storage] * nt / (sp * m * 1e-3) / 1e9 / HBM_PEAK_GBS}
             del s
             if args.precision_steps > 0:
                 s = make_sim(wt, "complete", storage, "ab", tf)

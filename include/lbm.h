@@ -143,6 +143,13 @@ lbm_status lbm_adjoint_populations(lbm_ctx* ctx, const void* d_fbarN, void* d_fb
 /* Completed time steps n, or -1 for a NULL context. */
 int64_t lbm_time(const lbm_ctx* ctx);
 
+/* Time steps one kernel launch of lbm_step advances for this context outside a recorded
+ * segment: 2 where the two-step LDS-staged kernel applies (A-B pattern, FP32 or FP64
+ * storage, nx a multiple of 64, ceil(nx/64) a multiple of 8, more than 2^15 storage
+ * positions), else 1 (-1 for a NULL context). Results do not depend on it: two steps in
+ * one launch are bit-identical to two single steps. */
+int32_t lbm_steps_per_launch(const lbm_ctx* ctx);
+
 const char* lbm_status_string(lbm_status s);
 
 /* Thread-local text of the last failure on the calling thread ("" if none). */

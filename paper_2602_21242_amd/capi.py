@@ -68,6 +68,8 @@ def lib():
         L.lbm_adjoint_populations.argtypes = [_vp, _vp, _vp]
         L.lbm_time.restype = ctypes.c_int64
         L.lbm_time.argtypes = [_vp]
+        L.lbm_steps_per_launch.restype = ctypes.c_int32
+        L.lbm_steps_per_launch.argtypes = [_vp]
         L.lbm_status_string.restype = ctypes.c_char_p
         L.lbm_status_string.argtypes = [ctypes.c_int]
         L.lbm_last_error.restype = ctypes.c_char_p
@@ -147,6 +149,10 @@ def lbm_adjoint_populations(ctx, d_fbarN, d_fbar0):
 
 def lbm_time(ctx):
     return lib().lbm_time(ctx)
+
+
+def lbm_steps_per_launch(ctx):
+    return lib().lbm_steps_per_launch(ctx)
 
 
 def lbm_status_string(s):

@@ -168,6 +168,16 @@ namespace {
   } while (0)
 
 template <class F>
+bool dispatch_bool(int storage, F&& f) {
+  switch (storage) {
+    case LBM_F64: return f(lbm::Engine<double>{});
+    case LBM_F32: return f(lbm::Engine<float>{});
+    case LBM_F16: return f(lbm::Engine<_Float16>{});
+    default: return f(lbm::Engine<lbm::bf16_t>{});
+  }
+}
+
+template <class F>
 lbm_status dispatch(int storage, F&& f) {
   switch (storage) {
     case LBM_F64: return f(lbm::Engine<double>{});
@@ -199,6 +209,25 @@ lbm_status do_step(lbm_ctx* c, void* rec) {
     ++c->time;
     return LBM_OK;
   });
+}
+
+// Two A-B steps in one launch (the LDS-staged kernel).
+lbm_status do_step2(lbm_ctx* c) {
+  return dispatch(c->p.storage, [&](auto eng) -> lbm_status {
+    using E = decltype(eng);
+    const hipError_t e = E::step2(c->d, c->ws + c->plan.pop_off[c->cur], c->ws + c->plan.pop_off[1 - c->cur], c->stream);
+    if (e != hipSuccess) return fail(LBM_ERR_HIP, std::string("two-step kernel launch: ") + hipGetErrorString(e));
+    c->cur ^= 1;
+    c->time += 2;
+    return LBM_OK;
+  });
+}
+
+bool is_small(const lbm_ctx* c) { return int64_t(c->d.pitch) * c->d.ny <= kGraphMaxPositions; }
+
+bool fused_ok(const lbm_ctx* c) {
+  if (c->p.pattern != LBM_AB) return false;
+  return dispatch_bool(c->p.storage, [&](auto eng) { return decltype(eng)::fused_ok(c->d); });
 }
 
 // The executable graph of kGraphSteps steps from the current buffer index (A-B) or phase
@@ -384,9 +413,16 @@ lbm_status lbm_step(lbm_ctx* c, int64_t n) {
     if (n < 0) return fail(LBM_ERR_INVALID_ARGUMENT, "n must be >= 0");
     DeviceGuard g(c->device);
     const int64_t N = c->p.record_steps;
-    const bool small = int64_t(c->d.pitch) * c->d.ny <= kGraphMaxPositions;
+    const bool small = is_small(c);
+    const bool fused = !small && fused_ok(c);
     for (int64_t k = 0; k < n;) {
       const bool recording = N > 0 && c->rec_valid && c->time < N;
+      if (fused && !recording && n - k >= 2) {
+        s = do_step2(c);
+        if (s != LBM_OK) return s;
+        k += 2;
+        continue;
+      }
       if (small && !recording && n - k >= kGraphSteps) {
         hipGraphExec_t ge = nullptr;
         s = step_graph(c, &ge);
@@ -533,6 +569,11 @@ lbm_status lbm_adjoint_populations(lbm_ctx* c, const void* d_fbarN, void* d_fbar
       return restore(c, c->plan.nck, N);
     });
   });
+}
+
+int32_t lbm_steps_per_launch(const lbm_ctx* c) {
+  if (!c) return -1;
+  return (!is_small(c) && fused_ok(c)) ? 2 : 1;
 }
 
 int64_t lbm_time(const lbm_ctx* c) { return c ? c->time : -1; }

@@ -33,6 +33,10 @@ template <class S>
 struct Engine {
   using T = typename StorageTraits<S>::T;
   static hipError_t step(const RunDesc& d, int phase, const void* src, void* dst, void* rec, hipStream_t st);
+  // Two A-B steps in one launch (src and dst distinct); fused_ok tells whether the grid and
+  // the storage type allow it.
+  static bool fused_ok(const RunDesc& d);
+  static hipError_t step2(const RunDesc& d, const void* src, void* dst, hipStream_t st);
   static hipError_t init(const RunDesc& d, LayoutSel L, void* buf, const double* rho, const double* ux,
                          const double* uy, hipStream_t st);
   static hipError_t get(const RunDesc& d, LayoutSel L, const void* buf, bool out_f64, void* out, hipStream_t st);

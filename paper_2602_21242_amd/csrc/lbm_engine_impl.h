@@ -325,6 +325,42 @@ hipError_t Engine<S>::step(const RunDesc& d, int phase, const void* src, void* d
   }
 }
 
+template <class S, int MODEL>
+hipError_t launch_step2_m(const RunDesc& d, const void* src, void* dst, hipStream_t st) {
+  using T = typename StorageTraits<S>::T;
+  const Geo g = make_geo(d, 1);
+  const Coef<T> k = make_coef<T>(d);
+  const dim3 grid(unsigned(g.S / kFuseGroups), unsigned((d.ny + kFuseRows - 1) / kFuseRows));
+  hipLaunchKernelGGL((k_step2<S, MODEL>), grid, dim3((kFuseGroups + 2) * kLanes), 0, st, static_cast<const S*>(src),
+                     static_cast<S*>(dst), g, k);
+  return hipGetLastError();
+}
+
+// Storage types served by the two-step kernel. Measured on MI355X, complete model, GLUPS
+// single-step / two-step: FP32 89.7 / 134.5 (4096^2), FP64 42.0 / 71.4 (8192^2); the 16-bit
+// paths, whose single-step kernels are already limited by arithmetic rather than bandwidth,
+// lose (FP16 167 / 144, BF16 170 / 160).
+template <class S> struct FuseSteps { static constexpr bool value = false; };
+template <> struct FuseSteps<float> { static constexpr bool value = true; };
+template <> struct FuseSteps<double> { static constexpr bool value = true; };
+
+template <class S>
+bool Engine<S>::fused_ok(const RunDesc& d) {
+  return FuseSteps<S>::value && d.nx % kLanes == 0 && (d.pitch / kLanes) % kFuseGroups == 0 &&
+         d.ny <= 65535 * kFuseRows;
+}
+
+template <class S>
+hipError_t Engine<S>::step2(const RunDesc& d, const void* src, void* dst, hipStream_t st) {
+  if (!fused_ok(d)) return hipErrorInvalidValue;
+  switch (d.model) {
+    case M_BGK: return launch_step2_m<S, M_BGK>(d, src, dst, st);
+    case M_UC: return launch_step2_m<S, M_UC>(d, src, dst, st);
+    case M_PARTIAL: return launch_step2_m<S, M_PARTIAL>(d, src, dst, st);
+    default: return launch_step2_m<S, M_COMPLETE>(d, src, dst, st);
+  }
+}
+
 template <class S>
 hipError_t Engine<S>::init(const RunDesc& d, LayoutSel L, void* buf, const double* rho, const double* ux,
                            const double* uy, hipStream_t st) {

@@ -186,6 +186,91 @@ k_step(const S* src, S* dst, Geo geo, Coef<typename StorageTraits<S>::T> k,
   }
 }
 
+// Two time steps per launch (A-B pattern), staged through LDS. A block owns kFuseGroups
+// consecutive groups (one interior wavefront each) and the rows [y0, y0 + kFuseRows); two
+// halo wavefronts compute the x-neighbours of its edge groups. The block walks its rows
+// y0 - 1 .. y1: phase A computes step 1 of every wavefront's node at row r from global
+// memory (pull) into a ring of three rows in LDS, rounded to the storage type exactly as
+// the single-step kernel would store it; phase B computes step 2 of row r - 1 for the
+// interior wavefronts, pulling from the ring, and stores it. The loads of row r + 1 are
+// issued before the barrier so that they overlap phase B. Every population is read once and
+// written once per two steps (plus the halo's reads), and the result is bit-identical to
+// two single steps: the halo nodes' step 1 is the same computation on the same inputs.
+// Requires nx % 64 == 0 (no padding, so the interior x-neighbours of a group are the
+// adjacent groups of the same lane) and S % kFuseGroups == 0.
+constexpr int kFuseGroups = 8;
+constexpr int kFuseRows = 64;
+
+template <class S>
+__device__ __forceinline__ void load_pulled(const S* src, const Geo& geo, int r, const RowPos& rp, S gs[Q]) {
+  const int y = r < 0 ? r + geo.ny : (r >= geo.ny ? r - geo.ny : r);
+  const int ym = (y == 0) ? geo.ny - 1 : y - 1;
+  const int yp = (y == geo.ny - 1) ? 0 : y + 1;
+  const size_t rsb = size_t(geo.rs) * sizeof(S), psb = size_t(geo.ps) * sizeof(S);
+  const char* sr[3] = {reinterpret_cast<const char*>(src) + ym * rsb, reinterpret_cast<const char*>(src) + y * rsb,
+                       reinterpret_cast<const char*>(src) + yp * rsb};
+  static_for<0, Q>([&](auto I) {
+    constexpr int i = decltype(I)::value;
+    gs[i] = ld1(at<S>(sr[-cy(i) + 1] + i * psb, rp.template of<-cx(i)>()));
+  });
+}
+
+template <class S, int MODEL>
+__global__ void __launch_bounds__((kFuseGroups + 2) * kLanes)
+k_step2(const S* __restrict__ src, S* __restrict__ dst, Geo geo, Coef<typename StorageTraits<S>::T> k) {
+  using T = typename StorageTraits<S>::T;
+  using Tr = StorageTraits<S>;
+  constexpr int G = kFuseGroups;
+  __shared__ S ring[3][G + 2][Q][kLanes];
+  const int w = __builtin_amdgcn_readfirstlane(int(threadIdx.x / kLanes));
+  const int lane = int(threadIdx.x % kLanes);
+  const int s0 = int(blockIdx.x) * G;
+  const int y0 = int(blockIdx.y) * kFuseRows;
+  const int y1 = min(y0 + kFuseRows, geo.ny);
+  // Phase-A node: the wavefront's own group (w = 1..G) or the x-neighbour of an edge group.
+  RowPos ra;
+  if (w == 0 || w == G + 1) {
+    RowPos e;
+    node_pos(geo, w == 0 ? s0 : s0 + G - 1, lane, e);
+    const int p = w == 0 ? e.pm : e.pp;
+    node_pos(geo, p / kLanes, p % kLanes, ra);
+  } else {
+    node_pos(geo, s0 + w - 1, lane, ra);
+  }
+  const bool interior = w >= 1 && w <= G;
+  const int pb = (s0 + w - 1) * kLanes + lane;  // phase-B output position
+  const size_t rsb = size_t(geo.rs) * sizeof(S), psb = size_t(geo.ps) * sizeof(S);
+
+  S gs[Q];
+  load_pulled<S>(src, geo, y0 - 1, ra, gs);
+  for (int r = y0 - 1; r <= y1; ++r) {
+    const int slot = (r - y0 + 1) % 3;
+    {
+      T g[Q], out[Q];
+#pragma unroll
+      for (int i = 0; i < Q; ++i) g[i] = Tr::load(gs[i]);
+      collide<T, MODEL>(g, out, k, nullptr);
+#pragma unroll
+      for (int i = 0; i < Q; ++i) ring[slot][w][i][lane] = Tr::store(out[i]);
+    }
+    if (r < y1) load_pulled<S>(src, geo, r + 1, ra, gs);
+    __syncthreads();
+    if (interior && r > y0) {
+      const int yr = r - 1;
+      T g[Q], out[Q];
+      static_for<0, Q>([&](auto I) {
+        constexpr int i = decltype(I)::value;
+        g[i] = Tr::load(ring[(yr - cy(i) - y0 + 1) % 3][w - cx(i)][i][lane]);
+      });
+      collide<T, MODEL>(g, out, k, nullptr);
+      char* drow = reinterpret_cast<char*>(dst) + yr * rsb;
+#pragma unroll
+      for (int i = 0; i < Q; ++i) st1(at<S>(drow + i * psb, pb), Tr::store(out[i]));
+    }
+    __syncthreads();
+  }
+}
+
 // One reverse step of the discrete adjoint: fbar^n(x) = J(m^n(x))^T fbar*(x) with the
 // reverse-streamed fbar*_i(x) = fbar^{n+1}_i(x + c_i). fbar uses the population layout in
 // the compute type (geo describes it); rec holds the step's recorded moments.

@@ -63,6 +63,11 @@ class Simulation:
         return capi.lbm_time(self._ctx)
 
     @property
+    def steps_per_launch(self):
+        """Time steps one step-kernel launch advances (2 on the two-step kernel's grids)."""
+        return capi.lbm_steps_per_launch(self._ctx)
+
+    @property
     def shape(self):
         return self.params.ny, self.params.nx
 

@@ -32,7 +32,8 @@ def test_header_declares_the_boundary():
     names = _declared_functions()
     for required in ("lbm_init", "lbm_step", "lbm_moments", "lbm_adjoint", "lbm_workspace_bytes",
                      "lbm_invariants", "lbm_destroy", "lbm_time", "lbm_status_string", "lbm_last_error",
-                     "lbm_get_populations", "lbm_set_populations", "lbm_adjoint_populations"):
+                     "lbm_get_populations", "lbm_set_populations", "lbm_adjoint_populations",
+                     "lbm_steps_per_launch"):
         assert required in names
 
 
@@ -116,6 +117,7 @@ def test_null_context(capi):
     assert capi.lbm_invariants(None)[0] == capi.LBM_ERR_INVALID_ARGUMENT
     assert capi.lbm_adjoint(None, None, 1, 1, 1, 1) == capi.LBM_ERR_INVALID_ARGUMENT
     assert capi.lbm_time(None) == -1
+    assert capi.lbm_steps_per_launch(None) == -1
     capi.lbm_destroy(None)
 
 

@@ -240,3 +240,37 @@ def test_step_graph_replays_match_single_launches(storage, pattern):
         total += extra
     ref = oracle.run(oracle.init_equilibrium(*fields, th), th, nu, "complete", total)
     assert eps_f(a.populations().cpu().numpy(), ref) <= {"f64": 1e-12, "f32": 1e-5, "f16": 1e-3}[storage]
+
+
+@pytest.mark.parametrize("storage", ["f64", "f32", "f16", "bf16"])
+@pytest.mark.parametrize("model", ["bgk", "uc", "partial", "complete"])
+def test_two_step_kernel_matches_single_steps(storage, model):
+    """A-B runs of n >= 2 steps with FP32 or FP64 storage on grids with nx % 64 == 0 and
+    S % 8 == 0 advance two steps per launch through the LDS-staged kernel (the 16-bit types
+    keep single steps). 512 x 100 (the last block of rows is ragged),
+    7 steps (three fused launches and one single step) against a run advanced one
+    lbm_step(1) call at a time: bit for bit; then against the oracle."""
+    nx, ny, th, nu = 512, 100, 0.4, 0.02
+    f0 = inp.random_populations(nx, ny, seed=41, amp=0.02)
+    a = gpu_sim(nx, ny, th, nu, model, storage, "ab", f0=f0)
+    b = gpu_sim(nx, ny, th, nu, model, storage, "ab", f0=f0)
+    assert a.steps_per_launch == (2 if storage in ("f64", "f32") else 1)
+    a.step(7)
+    for _ in range(7):
+        b.step(1)
+    fa = a.populations().cpu().numpy()
+    assert np.array_equal(fa, b.populations().cpu().numpy())
+    ref = oracle.run(f0, th, nu, model, 7)
+    assert eps_f(fa, ref) <= {"f64": 1e-13, "f32": 1e-6}.get(storage, TOL[storage])
+
+
+
+def test_steps_per_launch_follows_the_eligibility_rule():
+    """Two steps per launch only for A-B, FP32/FP64, nx % 64 == 0, S % 8 == 0 and more than
+    2^15 storage positions; every other context launches one step at a time."""
+    cases = [((512, 100, "f32", "ab"), 2), ((512, 100, "f64", "ab"), 2), ((512, 100, "f32", "aa"), 1),
+             ((512, 100, "f16", "ab"), 1), ((500, 100, "f32", "ab"), 1), ((448, 100, "f32", "ab"), 1),
+             ((512, 60, "f32", "ab"), 1), ((4096, 16, "f32", "ab"), 2)]
+    for (nx, ny, storage, pattern), expect in cases:
+        sim = gpu_sim(nx, ny, 0.4, 0.02, "complete", storage, pattern)
+        assert sim.steps_per_launch == expect, (nx, ny, storage, pattern)
