@@ -77,6 +77,8 @@ typedef struct {
   int32_t pattern;       /* lbm_pattern */
   int32_t ckpt_stride;   /* adjoint checkpoint spacing in steps; 0: ceil(sqrt(record_steps)) */
   int64_t record_steps;  /* 0: no adjoint; N > 0: checkpoint the first N steps for lbm_adjoint */
+  int32_t two_step;      /* two steps per launch (see lbm_steps_per_launch): 0 where the grid is
+                            large enough for it to pay, 1 wherever the layout allows, -1 never */
 } lbm_params;
 
 typedef struct lbm_ctx lbm_ctx; /* opaque host-side context */
@@ -143,11 +145,14 @@ lbm_status lbm_adjoint_populations(lbm_ctx* ctx, const void* d_fbarN, void* d_fb
 /* Completed time steps n, or -1 for a NULL context. */
 int64_t lbm_time(const lbm_ctx* ctx);
 
-/* Time steps one kernel launch of lbm_step advances for this context outside a recorded
- * segment: 2 where the two-step LDS-staged kernel applies (A-B pattern, FP32 or FP64
- * storage, nx a multiple of 64, ceil(nx/64) a multiple of 8, more than 2^15 storage
- * positions), else 1 (-1 for a NULL context). Results do not depend on it: two steps in
- * one launch are bit-identical to two single steps. */
+/* Time steps one kernel launch of lbm_step advances for this context: 2 where the two-step
+ * LDS-staged kernel applies, else 1 (-1 for a NULL context). It applies to the A-B pattern
+ * with FP32 or FP64 storage, nx a multiple of 512, more than 2^15 storage positions and
+ * two_step >= 0; with two_step = 0 also only where the grid gives at least three quarters
+ * of the device's compute units a block of 2 or more rows x 512 columns (roughly
+ * (nx/512) floor(ny/2) >= 3 CUs/4), below which the single-step kernel is faster. A pair of steps never
+ * passes over a checkpoint time of a recorded run. Results do not depend on it: two steps
+ * in one launch are bit-identical to two single steps. */
 int32_t lbm_steps_per_launch(const lbm_ctx* ctx);
 
 const char* lbm_status_string(lbm_status s);

@@ -65,6 +65,7 @@ lbm_status validate(const lbm_params* p) {
   if (p->pattern != LBM_AB && p->pattern != LBM_AA) return fail(LBM_ERR_INVALID_ARGUMENT, "unknown pattern");
   if (p->record_steps < 0) return fail(LBM_ERR_INVALID_ARGUMENT, "record_steps must be >= 0");
   if (p->ckpt_stride < 0) return fail(LBM_ERR_INVALID_ARGUMENT, "ckpt_stride must be >= 0");
+  if (p->two_step < -1 || p->two_step > 1) return fail(LBM_ERR_INVALID_ARGUMENT, "two_step must be -1, 0 or 1");
   return LBM_OK;
 }
 
@@ -168,7 +169,7 @@ namespace {
   } while (0)
 
 template <class F>
-bool dispatch_bool(int storage, F&& f) {
+int dispatch_int(int storage, F&& f) {
   switch (storage) {
     case LBM_F64: return f(lbm::Engine<double>{});
     case LBM_F32: return f(lbm::Engine<float>{});
@@ -211,13 +212,14 @@ lbm_status do_step(lbm_ctx* c, void* rec) {
   });
 }
 
-// Two A-B steps in one launch (the LDS-staged kernel).
-lbm_status do_step2(lbm_ctx* c) {
+// Two A-B steps in one launch (the LDS-staged kernel) from src into population buffer dst,
+// which then holds the state; rec1/rec2 (or null) receive both steps' moment records.
+lbm_status do_step2(lbm_ctx* c, const void* src, int dst, void* rec1, void* rec2) {
   return dispatch(c->p.storage, [&](auto eng) -> lbm_status {
     using E = decltype(eng);
-    const hipError_t e = E::step2(c->d, c->ws + c->plan.pop_off[c->cur], c->ws + c->plan.pop_off[1 - c->cur], c->stream);
+    const hipError_t e = E::step2(c->d, src, c->ws + c->plan.pop_off[dst], rec1, rec2, c->stream);
     if (e != hipSuccess) return fail(LBM_ERR_HIP, std::string("two-step kernel launch: ") + hipGetErrorString(e));
-    c->cur ^= 1;
+    c->cur = dst;
     c->time += 2;
     return LBM_OK;
   });
@@ -225,10 +227,7 @@ lbm_status do_step2(lbm_ctx* c) {
 
 bool is_small(const lbm_ctx* c) { return int64_t(c->d.pitch) * c->d.ny <= kGraphMaxPositions; }
 
-bool fused_ok(const lbm_ctx* c) {
-  if (c->p.pattern != LBM_AB) return false;
-  return dispatch_bool(c->p.storage, [&](auto eng) { return decltype(eng)::fused_ok(c->d); });
-}
+bool fused_ok(const lbm_ctx* c) { return c->d.fuse_rb > 0; }
 
 // The executable graph of kGraphSteps steps from the current buffer index (A-B) or phase
 // parity (AA). It is recorded by running the ordinary step launches against the private
@@ -289,18 +288,23 @@ lbm_status restore(lbm_ctx* c, int64_t slot, int64_t t) {
 
 // Reverse sweep over the recorded run: on entry fbar(0) holds dJ/df^N; on exit fbar(*out_b)
 // holds dJ/df^0. Segment k (steps [k s, min((k+1) s, N))) is recomputed from its checkpoint
-// while recording moments (the first step reads the checkpoint slot directly, so no copy
-// restores it), then traversed backwards with the adjoint kernel.
+// while recording moments (two steps per launch where the two-step kernel applies; the
+// first launch reads the checkpoint slot directly, so no copy restores it), then traversed
+// backwards with the adjoint kernel.
 lbm_status sweep(lbm_ctx* c, int* out_b) {
   const int64_t N = c->p.record_steps, s = c->plan.stride;
   int b = 0;
   for (int64_t k = c->plan.nck - 1; k >= 0; --k) {
     const int64_t t0 = k * s, t1 = std::min(t0 + s, N);
     c->time = t0;
-    lbm_status st = step_from(c, c->ckpt(k), c->rec_slot(0));
+    const bool fz = fused_ok(c);
+    lbm_status st = (fz && t1 - t0 >= 2) ? do_step2(c, c->ckpt(k), 0, c->rec_slot(0), c->rec_slot(1))
+                                         : step_from(c, c->ckpt(k), c->rec_slot(0));
     if (st != LBM_OK) return st;
-    for (int64_t t = t0 + 1; t < t1; ++t) {
-      st = do_step(c, c->rec_slot(t - t0));
+    while (c->time < t1) {
+      const int64_t j = c->time - t0;
+      st = (fz && t1 - c->time >= 2) ? do_step2(c, c->state(), 1 - c->cur, c->rec_slot(j), c->rec_slot(j + 1))
+                                     : do_step(c, c->rec_slot(j));
       if (st != LBM_OK) return st;
     }
     for (int64_t t = t1 - 1; t >= t0; --t) {
@@ -388,6 +392,9 @@ lbm_status lbm_init(const lbm_params* p, void* d_workspace, size_t workspace_byt
     d.rho0 = p->rho0;
     d.tau = p->nu / p->theta + 0.5;  // nu = theta (tau - 1/2)
     d.model = p->model;
+    d.fuse_rb = (p->pattern == LBM_AB && p->two_step >= 0)
+                    ? dispatch_int(p->storage, [&](auto eng) { return decltype(eng)::fuse_row_blocks(d, p->two_step); })
+                    : 0;
     c->time = 0;
     c->cur = 0;
     c->rec_valid = p->record_steps > 0;
@@ -417,8 +424,13 @@ lbm_status lbm_step(lbm_ctx* c, int64_t n) {
     const bool fused = !small && fused_ok(c);
     for (int64_t k = 0; k < n;) {
       const bool recording = N > 0 && c->rec_valid && c->time < N;
-      if (fused && !recording && n - k >= 2) {
-        s = do_step2(c);
+      if (recording && c->time % c->plan.stride == 0)
+        HIP_TRY(hipMemcpyAsync(c->ckpt(c->time / c->plan.stride), c->state(), c->plan.pop_bytes,
+                               hipMemcpyDeviceToDevice, c->stream));
+      // A pair of steps must not pass over a checkpoint time of the recorded window.
+      const int64_t mid = c->time + 1;
+      if (fused && n - k >= 2 && !(recording && mid < N && mid % c->plan.stride == 0)) {
+        s = do_step2(c, c->state(), 1 - c->cur, nullptr, nullptr);
         if (s != LBM_OK) return s;
         k += 2;
         continue;
@@ -432,9 +444,6 @@ lbm_status lbm_step(lbm_ctx* c, int64_t n) {
         k += kGraphSteps;
         continue;
       }
-      if (recording && c->time % c->plan.stride == 0)
-        HIP_TRY(hipMemcpyAsync(c->ckpt(c->time / c->plan.stride), c->state(), c->plan.pop_bytes,
-                               hipMemcpyDeviceToDevice, c->stream));
       s = do_step(c, nullptr);
       if (s != LBM_OK) return s;
       ++k;

@@ -20,6 +20,7 @@ struct RunDesc {
   int64_t rs_rec;     // row stride of a recorded-moment slot (5 * pitch)
   double theta, nu, rho0, tau;
   int model;         // M_BGK ... M_COMPLETE
+  int fuse_rb;       // row blocks of the two-step kernel; 0: one step per launch
 };
 
 // State layout at a given time: f_i(x) = buf[swap ? opp(i) : i][x - shift c_i].
@@ -33,10 +34,12 @@ template <class S>
 struct Engine {
   using T = typename StorageTraits<S>::T;
   static hipError_t step(const RunDesc& d, int phase, const void* src, void* dst, void* rec, hipStream_t st);
-  // Two A-B steps in one launch (src and dst distinct); fused_ok tells whether the grid and
-  // the storage type allow it.
-  static bool fused_ok(const RunDesc& d);
-  static hipError_t step2(const RunDesc& d, const void* src, void* dst, hipStream_t st);
+  // Two A-B steps in one launch (src and dst distinct) over d.fuse_rb row blocks, recording
+  // both steps' moments to rec1/rec2 when they are not null. fuse_row_blocks gives the row
+  // blocks for the current device (mode 0: only where it pays, 1: wherever the layout and
+  // the storage type allow it), or 0 for one step per launch.
+  static int fuse_row_blocks(const RunDesc& d, int mode);
+  static hipError_t step2(const RunDesc& d, const void* src, void* dst, void* rec1, void* rec2, hipStream_t st);
   static hipError_t init(const RunDesc& d, LayoutSel L, void* buf, const double* rho, const double* ux,
                          const double* uy, hipStream_t st);
   static hipError_t get(const RunDesc& d, LayoutSel L, const void* buf, bool out_f64, void* out, hipStream_t st);

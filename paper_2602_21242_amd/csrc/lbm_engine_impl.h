@@ -326,13 +326,20 @@ hipError_t Engine<S>::step(const RunDesc& d, int phase, const void* src, void* d
 }
 
 template <class S, int MODEL>
-hipError_t launch_step2_m(const RunDesc& d, const void* src, void* dst, hipStream_t st) {
+hipError_t launch_step2_m(const RunDesc& d, const void* src, void* dst, void* rec1, void* rec2, hipStream_t st) {
   using T = typename StorageTraits<S>::T;
   const Geo g = make_geo(d, 1);
   const Coef<T> k = make_coef<T>(d);
-  const dim3 grid(unsigned(g.S / kFuseGroups), unsigned((d.ny + kFuseRows - 1) / kFuseRows));
-  hipLaunchKernelGGL((k_step2<S, MODEL>), grid, dim3((kFuseGroups + 2) * kLanes), 0, st, static_cast<const S*>(src),
-                     static_cast<S*>(dst), g, k);
+  const dim3 grid(unsigned(g.S / kFuseGroups), unsigned(d.fuse_rb));
+  const dim3 block((kFuseGroups + 2) * kLanes);
+  const S* s = static_cast<const S*>(src);
+  S* o = static_cast<S*>(dst);
+  T* r1 = static_cast<T*>(rec1);
+  T* r2 = static_cast<T*>(rec2);
+  if (rec1 && rec2)
+    hipLaunchKernelGGL((k_step2<S, MODEL, true>), grid, block, 0, st, s, o, g, k, r1, r2, d.rs_rec);
+  else
+    hipLaunchKernelGGL((k_step2<S, MODEL, false>), grid, block, 0, st, s, o, g, k, r1, r2, d.rs_rec);
   return hipGetLastError();
 }
 
@@ -344,20 +351,46 @@ template <class S> struct FuseSteps { static constexpr bool value = false; };
 template <> struct FuseSteps<float> { static constexpr bool value = true; };
 template <> struct FuseSteps<double> { static constexpr bool value = true; };
 
+// Row blocks of the two-step kernel. A block of h rows computes h + 2 rows of step 1 and h
+// of step 2, and a compute unit works through its share of the blocks in turn, so a launch
+// takes about ceil(blocks / CUs) (2 h + 2) row-steps of one block, h the tallest block.
+// The planner takes the row-block count of least such cost with blocks of kFuseMinRows to
+// kFuseRows rows (ties: the taller blocks); for each count of blocks per compute unit only
+// the largest row-block count that keeps it needs checking. On MI355X this ranking matched
+// the measured throughput of every candidate tried on 512^2 to 4096^2 grids. In mode 0 a
+// grid that cannot give three quarters of the compute units a block keeps single steps.
 template <class S>
-bool Engine<S>::fused_ok(const RunDesc& d) {
-  return FuseSteps<S>::value && d.nx % kLanes == 0 && (d.pitch / kLanes) % kFuseGroups == 0 &&
-         d.ny <= 65535 * kFuseRows;
+int Engine<S>::fuse_row_blocks(const RunDesc& d, int mode) {
+  if (!FuseSteps<S>::value || d.nx % kLanes != 0 || (d.pitch / kLanes) % kFuseGroups != 0) return 0;
+  int dev = 0, cus = 0;
+  if (hipGetDevice(&dev) != hipSuccess ||
+      hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus < 1)
+    return 0;
+  const long ny = d.ny, cols = d.pitch / kLanes / kFuseGroups;
+  const long nb_lo = (ny + kFuseRows - 1) / kFuseRows;
+  const long nb_hi = std::min(std::max(nb_lo, ny / kFuseMinRows), 65535L);
+  if (nb_lo > nb_hi) return 0;
+  long best = 0, best_cost = 0;
+  const long w0 = std::max(1L, (cols * nb_lo + cus - 1) / cus);
+  for (long w = w0; w < w0 + 4096; ++w) {
+    const long nb = std::min(nb_hi, std::max(nb_lo, w * cus / cols));
+    const long rows = (ny + nb - 1) / nb;
+    const long cost = (cols * nb + cus - 1) / cus * (2 * rows + 2);
+    if (best == 0 || cost < best_cost) best = nb, best_cost = cost;
+    if (nb == nb_hi) break;
+  }
+  if (mode == 0 && 4 * cols * best < 3L * cus) return 0;
+  return int(best);
 }
 
 template <class S>
-hipError_t Engine<S>::step2(const RunDesc& d, const void* src, void* dst, hipStream_t st) {
-  if (!fused_ok(d)) return hipErrorInvalidValue;
+hipError_t Engine<S>::step2(const RunDesc& d, const void* src, void* dst, void* rec1, void* rec2, hipStream_t st) {
+  if (d.fuse_rb < 1 || d.fuse_rb > d.ny) return hipErrorInvalidValue;
   switch (d.model) {
-    case M_BGK: return launch_step2_m<S, M_BGK>(d, src, dst, st);
-    case M_UC: return launch_step2_m<S, M_UC>(d, src, dst, st);
-    case M_PARTIAL: return launch_step2_m<S, M_PARTIAL>(d, src, dst, st);
-    default: return launch_step2_m<S, M_COMPLETE>(d, src, dst, st);
+    case M_BGK: return launch_step2_m<S, M_BGK>(d, src, dst, rec1, rec2, st);
+    case M_UC: return launch_step2_m<S, M_UC>(d, src, dst, rec1, rec2, st);
+    case M_PARTIAL: return launch_step2_m<S, M_PARTIAL>(d, src, dst, rec1, rec2, st);
+    default: return launch_step2_m<S, M_COMPLETE>(d, src, dst, rec1, rec2, st);
   }
 }
 

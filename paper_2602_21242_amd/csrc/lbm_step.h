@@ -187,7 +187,8 @@ k_step(const S* src, S* dst, Geo geo, Coef<typename StorageTraits<S>::T> k,
 }
 
 // Two time steps per launch (A-B pattern), staged through LDS. A block owns kFuseGroups
-// consecutive groups (one interior wavefront each) and the rows [y0, y0 + kFuseRows); two
+// consecutive groups (one interior wavefront each) and the rows [y0, y1), the rows split
+// evenly over gridDim.y row blocks (so gridDim.y <= ny); two
 // halo wavefronts compute the x-neighbours of its edge groups. The block walks its rows
 // y0 - 1 .. y1: phase A computes step 1 of every wavefront's node at row r from global
 // memory (pull) into a ring of three rows in LDS, rounded to the storage type exactly as
@@ -197,9 +198,12 @@ k_step(const S* src, S* dst, Geo geo, Coef<typename StorageTraits<S>::T> k,
 // written once per two steps (plus the halo's reads), and the result is bit-identical to
 // two single steps: the halo nodes' step 1 is the same computation on the same inputs.
 // Requires nx % 64 == 0 (no padding, so the interior x-neighbours of a group are the
-// adjacent groups of the same lane) and S % kFuseGroups == 0.
+// adjacent groups of the same lane) and S % kFuseGroups == 0. A block recomputes two halo
+// rows of step 1 and reads four extra rows, so the host keeps blocks as tall as the grid
+// allows while still giving every compute unit work, between kFuseMinRows and kFuseRows.
 constexpr int kFuseGroups = 8;
 constexpr int kFuseRows = 64;
+constexpr int kFuseMinRows = 2;
 
 template <class S>
 __device__ __forceinline__ void load_pulled(const S* src, const Geo& geo, int r, const RowPos& rp, S gs[Q]) {
@@ -215,9 +219,13 @@ __device__ __forceinline__ void load_pulled(const S* src, const Geo& geo, int r,
   });
 }
 
-template <class S, int MODEL>
+// With REC the moments of both steps are recorded (rec1: first step, rec2: second step; the
+// layout and row stride rec_rs of k_step), by the interior wavefronts for the block's rows.
+template <class S, int MODEL, bool REC>
 __global__ void __launch_bounds__((kFuseGroups + 2) * kLanes)
-k_step2(const S* __restrict__ src, S* __restrict__ dst, Geo geo, Coef<typename StorageTraits<S>::T> k) {
+k_step2(const S* __restrict__ src, S* __restrict__ dst, Geo geo, Coef<typename StorageTraits<S>::T> k,
+        typename StorageTraits<S>::T* __restrict__ rec1, typename StorageTraits<S>::T* __restrict__ rec2,
+        int64_t rec_rs) {
   using T = typename StorageTraits<S>::T;
   using Tr = StorageTraits<S>;
   constexpr int G = kFuseGroups;
@@ -225,8 +233,8 @@ k_step2(const S* __restrict__ src, S* __restrict__ dst, Geo geo, Coef<typename S
   const int w = __builtin_amdgcn_readfirstlane(int(threadIdx.x / kLanes));
   const int lane = int(threadIdx.x % kLanes);
   const int s0 = int(blockIdx.x) * G;
-  const int y0 = int(blockIdx.y) * kFuseRows;
-  const int y1 = min(y0 + kFuseRows, geo.ny);
+  const int y0 = int(int64_t(blockIdx.y) * geo.ny / gridDim.y);
+  const int y1 = int(int64_t(blockIdx.y + 1) * geo.ny / gridDim.y);
   // Phase-A node: the wavefront's own group (w = 1..G) or the x-neighbour of an edge group.
   RowPos ra;
   if (w == 0 || w == G + 1) {
@@ -246,12 +254,19 @@ k_step2(const S* __restrict__ src, S* __restrict__ dst, Geo geo, Coef<typename S
   for (int r = y0 - 1; r <= y1; ++r) {
     const int slot = (r - y0 + 1) % 3;
     {
-      T g[Q], out[Q];
+      T g[Q], out[Q], rv[NREC];
 #pragma unroll
       for (int i = 0; i < Q; ++i) g[i] = Tr::load(gs[i]);
-      collide<T, MODEL>(g, out, k, nullptr);
+      collide<T, MODEL>(g, out, k, REC ? rv : nullptr);
 #pragma unroll
       for (int i = 0; i < Q; ++i) ring[slot][w][i][lane] = Tr::store(out[i]);
+      if constexpr (REC) {
+        if (interior && r >= y0 && r < y1) {
+          char* rrow = reinterpret_cast<char*>(rec1) + r * (size_t(rec_rs) * sizeof(T));
+#pragma unroll
+          for (int j = 0; j < NREC; ++j) st1(at<T>(rrow + j * size_t(geo.ps) * sizeof(T), pb), rv[j]);
+        }
+      }
     }
     if (r < y1) load_pulled<S>(src, geo, r + 1, ra, gs);
     __syncthreads();
@@ -262,7 +277,13 @@ k_step2(const S* __restrict__ src, S* __restrict__ dst, Geo geo, Coef<typename S
         constexpr int i = decltype(I)::value;
         g[i] = Tr::load(ring[(yr - cy(i) - y0 + 1) % 3][w - cx(i)][i][lane]);
       });
-      collide<T, MODEL>(g, out, k, nullptr);
+      T rv[NREC];
+      collide<T, MODEL>(g, out, k, REC ? rv : nullptr);
+      if constexpr (REC) {
+        char* rrow = reinterpret_cast<char*>(rec2) + yr * (size_t(rec_rs) * sizeof(T));
+#pragma unroll
+        for (int j = 0; j < NREC; ++j) st1(at<T>(rrow + j * size_t(geo.ps) * sizeof(T), pb), rv[j]);
+      }
       char* drow = reinterpret_cast<char*>(dst) + yr * rsb;
 #pragma unroll
       for (int i = 0; i < Q; ++i) st1(at<S>(drow + i * psb, pb), Tr::store(out[i]));

@@ -18,12 +18,15 @@ class Simulation:
 
     model: "bgk" | "uc" | "partial" | "complete"; storage: "f64" | "f32" | "bf16" | "f16";
     pattern: "ab" | "aa". record_steps > 0 checkpoints the first record_steps steps for
-    adjoint() (sqrt(N) checkpoints by default, or every ckpt_stride steps).
+    adjoint() (sqrt(N) checkpoints by default, or every ckpt_stride steps). two_step: 0 runs
+    two steps per launch where the grid is large enough for it to pay, 1 wherever the layout
+    allows, -1 never (results are bit-identical).
     """
 
     def __init__(self, nx, ny, theta, nu, ux, uy, rho=None, rho0=1.0, model="complete", storage="f32",
-                 pattern="ab", record_steps=0, ckpt_stride=0, device=None):
-        self.params = capi.make_params(nx, ny, theta, nu, rho0, model, storage, pattern, record_steps, ckpt_stride)
+                 pattern="ab", record_steps=0, ckpt_stride=0, two_step=0, device=None):
+        self.params = capi.make_params(nx, ny, theta, nu, rho0, model, storage, pattern, record_steps, ckpt_stride,
+                                       two_step)
         self.device = torch.device(device) if device is not None else torch.device("cuda", torch.cuda.current_device())
         s, nbytes = capi.lbm_workspace_bytes(self.params)
         capi.check(s, "lbm_workspace_bytes")
@@ -128,7 +131,7 @@ class LBMFunction(torch.autograd.Function):
 
     Usage: rho, ux, uy = LBMFunction.apply(ux0, uy0, config) with
     config = dict(nx=..., ny=..., theta=..., nu=..., steps=..., model=..., storage=...,
-    pattern=..., rho=None, rho0=1.0, ckpt_stride=0).
+    pattern=..., rho=None, rho0=1.0, ckpt_stride=0, two_step=0).
     """
 
     @staticmethod

@@ -76,7 +76,7 @@ def test_workspace_plan(capi, storage, esize, tsize, pattern, nbuf):
 
 BAD = [dict(nx=0), dict(ny=0), dict(nx=-3), dict(theta=0.0), dict(theta=1.0), dict(theta=float("nan")),
        dict(nu=0.0), dict(nu=-1e-3), dict(nu=float("inf")), dict(rho0=0.0), dict(model=4), dict(model=-1),
-       dict(storage=4), dict(pattern=2), dict(record_steps=-1), dict(ckpt_stride=-2),
+       dict(storage=4), dict(pattern=2), dict(record_steps=-1), dict(ckpt_stride=-2), dict(two_step=2), dict(two_step=-2),
        dict(nx=65536, ny=32768), dict(nx=65537, ny=32767), dict(nx=2 ** 31 - 63, ny=1)]
 
 

@@ -45,6 +45,30 @@ def test_population_adjoint_fp64(model, pattern):
         assert err <= 1e-12, (stride, err)
 
 
+@pytest.mark.parametrize("model", ["bgk", "complete"])
+@pytest.mark.parametrize("storage", ["f64", "f32"])
+def test_population_adjoint_with_two_step_launches(model, storage):
+    """With the two-step kernel asked for (512 x 100, two_step = 1), the recorded forward run and
+    the recomputation in the reverse sweep take two steps per launch (with moment records of
+    both), except where a pair would pass over a checkpoint time. N = 7 with spacings 3
+    (segments of 3, 3, 1 steps; the forward pair from step 2 would skip checkpoint 3), 2 and
+    the default: against the oracle's complex-step adjoint."""
+    import torch
+    nx, ny, th, nu, N = 512, 100, 0.4, 0.02, 7
+    f0 = inp.random_populations(nx, ny, seed=27, amp=0.05)
+    w = inp.random_direction((9, ny, nx), seed=28)
+    ref = _oracle_population_adjoint(f0, w, th, nu, model, N)
+    dtype = torch.float64 if storage == "f64" else torch.float32
+    for stride in (3, 2, 0):
+        sim = gpu_sim(nx, ny, th, nu, model, storage, "ab", f0=f0, record_steps=N, ckpt_stride=stride,
+                      two_step=1)
+        assert sim.steps_per_launch == 2
+        sim.step(N)
+        got = sim.adjoint_populations(_t(w, dtype)).cpu().numpy()
+        err = np.max(np.abs(got - ref)) / np.max(np.abs(ref))
+        assert err <= (1e-12 if storage == "f64" else 1e-5), (stride, err)
+
+
 @pytest.mark.parametrize("model", MODELS)
 def test_velocity_gradient_fp64_matches_oracle(model):
     """Gradient of the final kinetic energy E = 1/2 sum rho |u|^2 with respect to the initial

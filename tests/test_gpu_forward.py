@@ -245,15 +245,15 @@ def test_step_graph_replays_match_single_launches(storage, pattern):
 @pytest.mark.parametrize("storage", ["f64", "f32", "f16", "bf16"])
 @pytest.mark.parametrize("model", ["bgk", "uc", "partial", "complete"])
 def test_two_step_kernel_matches_single_steps(storage, model):
-    """A-B runs of n >= 2 steps with FP32 or FP64 storage on grids with nx % 64 == 0 and
-    S % 8 == 0 advance two steps per launch through the LDS-staged kernel (the 16-bit types
-    keep single steps). 512 x 100 (the last block of rows is ragged),
+    """A-B runs of n >= 2 steps with FP32 or FP64 storage on grids with nx % 512 == 0 advance
+    two steps per launch through the LDS-staged kernel when asked to (two_step = 1; the 16-bit
+    types keep single steps). 512 x 100 in blocks of 2 rows,
     7 steps (three fused launches and one single step) against a run advanced one
     lbm_step(1) call at a time: bit for bit; then against the oracle."""
     nx, ny, th, nu = 512, 100, 0.4, 0.02
     f0 = inp.random_populations(nx, ny, seed=41, amp=0.02)
-    a = gpu_sim(nx, ny, th, nu, model, storage, "ab", f0=f0)
-    b = gpu_sim(nx, ny, th, nu, model, storage, "ab", f0=f0)
+    a = gpu_sim(nx, ny, th, nu, model, storage, "ab", f0=f0, two_step=1)
+    b = gpu_sim(nx, ny, th, nu, model, storage, "ab", f0=f0, two_step=1)
     assert a.steps_per_launch == (2 if storage in ("f64", "f32") else 1)
     a.step(7)
     for _ in range(7):
@@ -264,13 +264,35 @@ def test_two_step_kernel_matches_single_steps(storage, model):
     assert eps_f(fa, ref) <= {"f64": 1e-13, "f32": 1e-6}.get(storage, TOL[storage])
 
 
+@pytest.mark.parametrize("storage", ["f64", "f32"])
+@pytest.mark.parametrize("nx,ny", [(1536, 1000), (2048, 777)])
+def test_two_step_kernel_uneven_row_blocks(storage, nx, ny):
+    """Grids whose rows do not split evenly over the two-step kernel's row blocks (on MI355X
+    85 blocks of 11-12 rows for 1536 x 1000, 64 blocks of 12-13 rows for 2048 x 777), with
+    the default choice of two steps per launch: 9 steps bit for bit against single steps."""
+    fields = inp.taylor_green(nx, ny, 0.05, 0.4, noise=1e-3, seed=6)
+    a = gpu_sim(nx, ny, 0.4, 0.02, "complete", storage, "ab", fields=fields)
+    b = gpu_sim(nx, ny, 0.4, 0.02, "complete", storage, "ab", fields=fields)
+    assert a.steps_per_launch == 2
+    a.step(9)
+    for _ in range(9):
+        b.step(1)
+    assert np.array_equal(a.populations().cpu().numpy(), b.populations().cpu().numpy())
+
+
 
 def test_steps_per_launch_follows_the_eligibility_rule():
-    """Two steps per launch only for A-B, FP32/FP64, nx % 64 == 0, S % 8 == 0 and more than
-    2^15 storage positions; every other context launches one step at a time."""
-    cases = [((512, 100, "f32", "ab"), 2), ((512, 100, "f64", "ab"), 2), ((512, 100, "f32", "aa"), 1),
-             ((512, 100, "f16", "ab"), 1), ((500, 100, "f32", "ab"), 1), ((448, 100, "f32", "ab"), 1),
-             ((512, 60, "f32", "ab"), 1), ((4096, 16, "f32", "ab"), 2)]
-    for (nx, ny, storage, pattern), expect in cases:
-        sim = gpu_sim(nx, ny, 0.4, 0.02, "complete", storage, pattern)
-        assert sim.steps_per_launch == expect, (nx, ny, storage, pattern)
+    """Two steps per launch only for A-B, FP32/FP64, nx % 512 == 0, more than 2^15 storage
+    positions and two_step >= 0; with two_step = 0 (the default) also only where the grid
+    gives at least three quarters of the compute units (256 on MI355X) a block of >= 2 rows
+    x 512 columns; every other context launches one step at a time."""
+    cases = [((512, 100, "f32", "ab", 1), 2), ((512, 100, "f64", "ab", 1), 2), ((512, 100, "f32", "aa", 1), 1),
+             ((512, 100, "f16", "ab", 1), 1), ((500, 100, "f32", "ab", 1), 1), ((448, 100, "f32", "ab", 1), 1),
+             ((512, 60, "f32", "ab", 1), 1), ((4096, 16, "f32", "ab", 1), 2),
+             ((512, 100, "f32", "ab", 0), 1), ((4096, 16, "f32", "ab", 0), 1), ((512, 256, "f32", "ab", 0), 1),
+             ((512, 512, "f32", "ab", 0), 2),
+             ((1024, 1024, "f64", "ab", 0), 2), ((2048, 2048, "f32", "ab", 0), 2), ((2048, 2048, "f32", "aa", 0), 1),
+             ((2048, 2048, "f32", "ab", -1), 1)]
+    for (nx, ny, storage, pattern, two_step), expect in cases:
+        sim = gpu_sim(nx, ny, 0.4, 0.02, "complete", storage, pattern, two_step=two_step)
+        assert sim.steps_per_launch == expect, (nx, ny, storage, pattern, two_step)
