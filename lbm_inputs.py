@@ -117,6 +117,15 @@ def double_shear_layer(nx, ny, u0, kappa, delta, rho0=1.0):
     return rho, ux, uy
 
 
+def shocktube(nx, rho_l=1.0, rho_r=0.5, ny=1):
+    """Isothermal shocktube on an nx x ny box with wall columns x = 0 and x = nx - 1: fluid at
+    rest, rho = rho_l for x < nx/2 and rho_r for x >= nx/2 (the jump between nodes nx/2 - 1
+    and nx/2); the wall nodes take the density of their side."""
+    x, y = _grid(nx, ny)
+    rho = np.where(x < nx // 2, rho_l, rho_r) + 0.0 * y
+    return rho, 0.0 * rho, 0.0 * rho
+
+
 def random_fields(nx, ny, seed, rho_spread=0.1, u_max=0.2, rho0=1.0):
     """Independent uniform random rho in rho0*[1-spread, 1+spread] and |u_a| <= u_max."""
     rng = np.random.default_rng(seed)

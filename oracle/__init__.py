@@ -35,6 +35,7 @@ def _load():
         lib.oracle_collide_node.argtypes = [_dp, ctypes.c_int, ctypes.c_double, ctypes.c_double, _dp]
         lib.oracle_init_equilibrium.argtypes = [_i64, _i64, ctypes.c_double, _dp, _dp, _dp, _dp]
         lib.oracle_run.argtypes = [_i64, _i64, ctypes.c_double, ctypes.c_double, ctypes.c_int, _i64, _dp]
+        lib.oracle_run_walls.argtypes = [_i64, _i64, ctypes.c_double, ctypes.c_double, ctypes.c_int, _i64, _dp]
         lib.oracle_moments.argtypes = [_i64, _i64, _dp, _dp, _dp, _dp]
         lib.oracle_invariants.argtypes = [_i64, _i64, _dp, _dp]
         lib.oracle_forward_fields.argtypes = [_i64, _i64, ctypes.c_double, ctypes.c_double, ctypes.c_int,
@@ -105,11 +106,16 @@ def init_equilibrium(rho, ux, uy, theta):
     return f
 
 
-def run(f, theta, nu, model, nsteps):
-    """Return f after nsteps time steps (input left unchanged)."""
+def run(f, theta, nu, model, nsteps, walls=False):
+    """Return f after nsteps time steps (input left unchanged). walls: the columns x = 0 and
+    x = nx - 1 are solid nodes with fullway bounce-back (nx >= 3)."""
     f = np.array(f, dtype=np.float64, order="C", copy=True)
     _, ny, nx = f.shape
-    _load().oracle_run(nx, ny, theta, nu, _model(model), int(nsteps), _ptr(f))
+    if walls:
+        assert nx >= 3
+        _load().oracle_run_walls(nx, ny, theta, nu, _model(model), int(nsteps), _ptr(f))
+    else:
+        _load().oracle_run(nx, ny, theta, nu, _model(model), int(nsteps), _ptr(f))
     return f
 
 

@@ -242,16 +242,30 @@ struct Grid {
   int64_t at(int i, int64_t y, int64_t x) const { return (int64_t(i) * ny + y) * nx + x; }
 };
 
+// The direction opposite to i: the j with c_j = -c_i, found in the velocity table.
+inline int opposite(int i) {
+  for (int j = 0; j < Q; ++j)
+    if (c[j][0] == -c[i][0] && c[j][1] == -c[i][1]) return j;
+  return -1;
+}
+
 // One time step: collide every node, then push each post-collision population to its
 // neighbour, f_i(x + c_i, t + 1) = f_i^*(x, t) (eq:lbe, second line), periodic box.
+// With walls, the columns x = 0 and x = nx - 1 are solid nodes with fullway bounce-back
+// (the shocktube of Sec. 5): instead of colliding, a wall node sends every population back
+// the way it came, f_i^*(x) = f_opposite(i)(x); the fluid nodes are x = 1 .. nx - 2.
 void lb_step(const Grid& g, int model, double theta, double tau, const double* f,
-             double* fnew) {
+             double* fnew, bool walls = false) {
 #pragma omp parallel for schedule(static)
   for (int64_t y = 0; y < g.ny; ++y) {
     for (int64_t x = 0; x < g.nx; ++x) {
       double fl[Q], fs[Q];
       for (int i = 0; i < Q; ++i) fl[i] = f[g.at(i, y, x)];
-      collide_only(fl, model, theta, tau, fs);
+      if (walls && (x == 0 || x == g.nx - 1)) {
+        for (int i = 0; i < Q; ++i) fs[i] = fl[opposite(i)];
+      } else {
+        collide_only(fl, model, theta, tau, fs);
+      }
       for (int i = 0; i < Q; ++i) {
         const int64_t yd = wrap(y + c[i][1], g.ny), xd = wrap(x + c[i][0], g.nx);
         fnew[g.at(i, yd, xd)] = fs[i];
@@ -352,6 +366,18 @@ void oracle_run(int64_t nx, int64_t ny, double theta, double nu, int model, int6
   std::vector<double> tmp(size_t(Q) * g.nodes());
   for (int64_t s = 0; s < nsteps; ++s) {
     lb_step(g, model, theta, tau, f, tmp.data());
+    std::memcpy(f, tmp.data(), sizeof(double) * tmp.size());
+  }
+}
+
+// oracle_run with solid bounce-back columns at x = 0 and x = nx - 1 (nx >= 3).
+void oracle_run_walls(int64_t nx, int64_t ny, double theta, double nu, int model, int64_t nsteps,
+                      double* f) {
+  Grid g{nx, ny};
+  const double tau = relaxation_time(theta, nu);
+  std::vector<double> tmp(size_t(Q) * g.nodes());
+  for (int64_t s = 0; s < nsteps; ++s) {
+    lb_step(g, model, theta, tau, f, tmp.data(), true);
     std::memcpy(f, tmp.data(), sizeof(double) * tmp.size());
   }
 }

@@ -42,5 +42,32 @@ def eps_f(f, fref):
     return float(np.max(np.abs(f - fref)) / np.max(np.abs(fref)))
 
 
+def isothermal_riemann(x, t, x0, rho_l, rho_r, c):
+    """Exact solution (rho, u) at positions x and time t > 0 of the isothermal Euler equations
+    rho_t + (rho u)_x = 0, (rho u)_t + (rho u^2 + c^2 rho)_x = 0 for a fluid at rest with
+    density rho_l left of x0 and rho_r < rho_l right of it: a left rarefaction, a plateau
+    (rho_m, u_m) and a right-moving shock. Along the rarefaction u + c ln rho is constant;
+    across the shock the jump conditions give u_m = c (rho_m - rho_r) / sqrt(rho_m rho_r).
+    rho_m solves c ln(rho_l / rho_m) = c (rho_m - rho_r) / sqrt(rho_m rho_r) (bisection).
+    Returns (rho, u, rho_m, u_m, shock speed)."""
+    assert rho_l > rho_r > 0 and t > 0
+    g = lambda r: math.log(rho_l / r) - (r - rho_r) / math.sqrt(r * rho_r)
+    lo, hi = rho_r, rho_l
+    for _ in range(200):
+        mid = 0.5 * (lo + hi)
+        if g(mid) > 0:
+            lo = mid
+        else:
+            hi = mid
+    rho_m = 0.5 * (lo + hi)
+    u_m = c * math.log(rho_l / rho_m)
+    s = rho_m * u_m / (rho_m - rho_r)
+    xi = (np.asarray(x, dtype=np.float64) - x0) / t
+    u_fan = xi + c
+    rho = np.where(xi < -c, rho_l, np.where(xi < u_m - c, rho_l * np.exp(-u_fan / c), np.where(xi < s, rho_m, rho_r)))
+    u = np.where(xi < -c, 0.0, np.where(xi < u_m - c, u_fan, np.where(xi < s, u_m, 0.0)))
+    return rho, u, rho_m, u_m, s
+
+
 def eps_u(u, uref):
     return float(np.max(np.abs(u - uref)) / np.max(np.abs(uref)))

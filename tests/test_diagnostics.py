@@ -3,6 +3,8 @@ mode amplitude and decay viscosity, vorticity of a sine field, thickness of a ta
 vortex-core count of separated Gaussian vortices."""
 import math
 
+import numpy as np
+
 import pytest
 import torch
 
@@ -57,3 +59,22 @@ def test_vortex_cores_counts_separated_vortices_across_the_wrap():
     om = g(0, 0, 4) - g(64, 70, 5) + 0.1 * g(30, 100, 3)    # the weak one is below 30 %
     assert d.vortex_cores(om) == 2
     assert d.vortex_cores(om, frac=0.05) == 3
+
+
+@pytest.mark.parametrize("c", [math.sqrt(1 / 3), math.sqrt(0.4), math.sqrt(0.55)])
+def test_isothermal_riemann_solution_satisfies_jump_conditions(c):
+    """The test-side exact shocktube solution: mass and momentum Rankine-Hugoniot conditions
+    at the shock, the rarefaction joining the left state to the plateau continuously, and
+    mass conservation of the whole profile (x in [0, 800], jump at 399.5, t = 400)."""
+    from tests.lbm_diag import isothermal_riemann
+    rl, rr = 1.0, 0.5
+    _, _, rm, um, s = isothermal_riemann(np.array([0.0]), 400.0, 399.5, rl, rr, c)
+    assert rr < rm < rl and um > 0 and s > um
+    assert abs(s * (rm - rr) - rm * um) <= 1e-12
+    assert abs(s * rm * um - (rm * um * um + c * c * rm - c * c * rr)) <= 1e-12
+    assert abs(rl * math.exp(-um / c) - rm) <= 1e-12
+    x = np.linspace(0.0, 800.0, 800001)
+    rho, u, *_ = isothermal_riemann(x, 400.0, 399.5, rl, rr, c)
+    mass = np.trapezoid(rho, x)
+    assert abs(mass - (rl * 399.5 + rr * 400.5)) <= 1e-3
+    assert rho[0] == rl and rho[-1] == rr and u[0] == 0.0 and u[-1] == 0.0

@@ -11,7 +11,7 @@ import pytest
 
 import lbm_inputs as inp
 import oracle
-from tests.lbm_diag import CX, CY, decay_viscosity, field_moments, mode_amplitude
+from tests.lbm_diag import CX, CY, decay_viscosity, field_moments, isothermal_riemann, mode_amplitude
 
 MODELS = ["bgk", "uc", "partial", "complete"]
 
@@ -163,3 +163,92 @@ def test_partial_model_unstable_at_low_temperature():
     dev = lambda g: np.max(np.abs(field_moments(g)[1]))
     assert not np.all(np.isfinite(fp)) or dev(fp) > 1e-3
     assert dev(fc) < 1e-6
+
+
+# ---------------------------------------------------------------------------------------
+# Solid columns with fullway bounce-back (the shocktube of Sec. 5).
+
+def test_wall_sends_a_population_back_the_way_it_came():
+    """With tau -> infinity (free streaming, as above) a marked north-east population (5)
+    pushed into the wall column x = 7 of an 8 x 6 box comes back as the south-west
+    population (7) along its own path: after 5 steps the mark sits in f_7 at (x, y) = (5, 2)
+    and nowhere else (a specular reflection would give f_6 instead)."""
+    nx, ny, th = 8, 6, 0.4
+    rest = oracle.init_equilibrium(np.ones((ny, nx)), np.zeros((ny, nx)), np.zeros((ny, nx)), th)
+    f0 = rest.copy()
+    f0[5, 1, 4] += 1e-3
+    d = oracle.run(f0, th, 1e300, "bgk", 5, walls=True) - rest
+    assert abs(d[7, 2, 5] - 1e-3) <= 1e-15
+    d[7, 2, 5] = 0.0
+    assert np.max(np.abs(d)) <= 1e-15
+
+
+@pytest.mark.parametrize("model", ["bgk", "uc", "partial", "complete"])
+def test_walls_keep_a_fluid_at_rest(model):
+    """Uniform density at rest between two wall columns stays exactly at rest."""
+    th = 0.4
+    f0 = oracle.init_equilibrium(np.full((3, 9), 1.3), np.zeros((3, 9)), np.zeros((3, 9)), th)
+    f = oracle.run(f0, th, 0.01, model, 50, walls=True)
+    assert np.max(np.abs(f - f0)) <= 1e-15
+
+
+@pytest.mark.parametrize("model", ["bgk", "uc", "partial", "complete"])
+def test_walls_conserve_mass(model):
+    """Random populations on 37 x 5 with wall columns: total mass (fluid and wall nodes) is
+    conserved, the bounce-back being a permutation of each wall node's populations."""
+    f0 = inp.random_populations(37, 5, seed=11)
+    f = oracle.run(f0, 0.4, 0.02, model, 30, walls=True)
+    assert abs(f.sum() - f0.sum()) <= 1e-13 * f0.sum()
+
+
+@pytest.mark.parametrize("model", ["bgk", "complete"])
+def test_walls_mirror_symmetry(model):
+    """A y-uniform state symmetric under x -> nx - 1 - x (rho even, u_x odd) stays symmetric:
+    the two walls reflect alike."""
+    nx, ny, th = 40, 3, 0.4
+    rng = np.random.default_rng(5)
+    r = 1.0 + 0.1 * rng.uniform(-1, 1, nx // 2)
+    v = 0.05 * rng.uniform(-1, 1, nx // 2)
+    rho = np.tile(np.concatenate([r, r[::-1]]), (ny, 1))
+    ux = np.tile(np.concatenate([v, -v[::-1]]), (ny, 1))
+    f = oracle.run(oracle.init_equilibrium(rho, ux, 0 * ux, th), th, 0.02, model, 40, walls=True)
+    rho1, ux1, uy1 = field_moments(f)
+    assert np.max(np.abs(rho1 - rho1[:, ::-1])) <= 1e-13
+    assert np.max(np.abs(ux1 + ux1[:, ::-1])) <= 1e-13
+    assert np.max(np.abs(uy1)) <= 1e-15
+
+
+@pytest.mark.parametrize("model", ["bgk", "complete"])
+def test_walls_are_no_slip(model):
+    """A wall-parallel velocity u_y = U sin(pi (x - 1/2) / L) between wall columns x = 0 and
+    x = L + 1 (theta = 1/3, nu = 0.05, L = 64) decays at nu (pi/L)^2: fullway bounce-back
+    puts a no-slip wall halfway between the wall column and the first fluid node (a
+    reflection that kept u_y would not damp this mode at the walls). Within 2 %."""
+    L, th, nu, U = 64, 1.0 / 3.0, 0.05, 1e-4
+    nx = L + 2
+    x = np.arange(nx, dtype=np.float64)
+    uy = np.where((x >= 1) & (x <= L), U * np.sin(math.pi * (x - 0.5) / L), 0.0)[None, :]
+    f = oracle.init_equilibrium(np.ones((1, nx)), 0 * uy, uy, th)
+    amp = lambda g: float(np.sum(field_moments(g)[2][0, 1:-1] * np.sin(math.pi * (x[1:-1] - 0.5) / L)))
+    f = oracle.run(f, th, nu, model, 200, walls=True)
+    a0 = amp(f)
+    f = oracle.run(f, th, nu, model, 1000, walls=True)
+    nu_m = -math.log(amp(f) / a0) / ((math.pi / L) ** 2 * 1000)
+    assert abs(nu_m / nu - 1) < 0.02, nu_m / nu
+
+
+@pytest.mark.parametrize("theta,nu,model,tol", [(1 / 3, 0.01, "bgk", 2e-4), (0.4, 1e-12, "complete", 2e-4),
+                                               (0.4, 1e-12, "partial", 2e-4), (0.55, 1e-9, "complete", 2e-4)])
+def test_shocktube_plateau_matches_exact_solution(theta, nu, model, tol):
+    """800 x 1 shocktube (walls at x = 0 and 799, rho = 1 | 0.5 at rest, 400 steps): the
+    density and velocity in the middle of the plateau between rarefaction and shock equal
+    the exact isothermal Riemann solution with sound speed sqrt(theta)."""
+    nx, T = 800, 400
+    c = math.sqrt(theta)
+    f = oracle.run(oracle.init_equilibrium(*inp.shocktube(nx), theta), theta, nu, model, T, walls=True)
+    rho, ux, _ = field_moments(f)
+    _, _, rm, um, s = isothermal_riemann(np.zeros(1), T, nx / 2 - 0.5, 1.0, 0.5, c)
+    xm = int(round(nx / 2 - 0.5 + T * 0.5 * (um - c + s)))
+    pl = slice(xm - 10, xm + 11)
+    assert abs(np.mean(rho[0, pl]) / rm - 1) <= tol
+    assert abs(np.mean(ux[0, pl]) / um - 1) <= 5 * tol
