@@ -173,11 +173,12 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--precision-steps", type=int, default=1000,
                     help="steps of the 8192^2 storage-precision comparison")
-    ap.add_argument("--only", choices=["adjoint", "precision", "viscosity", "shear-layer"], default=None,
+    ap.add_argument("--only", choices=["adjoint", "precision", "viscosity", "shear-layer", "shocktube"], default=None,
                     help="run only one section and print its JSON (adjoint: sweep and end-to-end gradient; "
                          "precision: storage types on the 8192^2 turbulence workload against the FP64 run; "
                          "viscosity: rotated shear-wave nu~/nu over theta, Mach number and model; "
-                         "shear-layer: the double shear layer at the paper's parameters over n, theta and model)")
+                         "shear-layer: the double shear layer at the paper's parameters over n, theta and model; "
+                         "shocktube: the isothermal shocktube between bounce-back walls against the exact solution)")
     ap.add_argument("--copy-probe", type=int, default=0,
                     help="only run a device-to-device copy of this many bytes (counter scaling)")
     args = ap.parse_args()
@@ -214,6 +215,9 @@ def main():
         return
     if args.only == "shear-layer":
         print(json.dumps(bench_shear_layer()), flush=True)
+        return
+    if args.only == "shocktube":
+        print(json.dumps(bench_shocktube()), flush=True)
         return
 
     w = inp.WORKLOADS[args.workload]
@@ -415,6 +419,27 @@ def bench_shear_layer(grids=(128, 256, 512), thetas=(0.4, 0.6), models=("bgk", "
         r.update(theta=th, n=n, model=m, seconds=time.perf_counter() - t1)
         runs.append(r)
     return {"workload": "double shear layer, u0=0.04, kappa=80, delta=0.05, Re=30000, 1 convective time, FP64",
+            "runs": runs, "seconds": time.perf_counter() - t0}
+
+
+def bench_shocktube(cases=((0.4, 1e-12), (0.55, 1e-9)), models=("bgk", "uc", "partial", "complete"),
+                    storages=("f64", "f32")):
+    """The isothermal shocktube of the paper's second benchmark: 800 x 1 between bounce-back
+    wall columns, rho = 1 | 0.5 at rest, 400 steps, per (theta, nu), model and storage type:
+    stability, plateau density and velocity against the exact isothermal Riemann solution,
+    mean absolute density error, and the density's total variation relative to the exact
+    one (spurious oscillations raise it above 1)."""
+    from paper_2602_21242_amd.diagnostics import shocktube_run
+    t0 = time.perf_counter()
+    runs = []
+    for th, nu in cases:
+        for st in storages:
+            for m in models:
+                log(f"[shocktube] theta {th} nu {nu:g} {m} {st}")
+                r = shocktube_run(m, th, nu, storage=st)
+                runs.append({"theta": th, "nu": nu, "model": m, "storage": st,
+                             **{k: v for k, v in r.items() if isinstance(v, (bool, int, float))}})
+    return {"workload": "isothermal shocktube 800x1, walls at x=0 and 799, rho 1|0.5, 400 steps",
             "runs": runs, "seconds": time.perf_counter() - t0}
 
 

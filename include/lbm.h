@@ -79,6 +79,14 @@ typedef struct {
   int64_t record_steps;  /* 0: no adjoint; N > 0: checkpoint the first N steps for lbm_adjoint */
   int32_t two_step;      /* two steps per launch (see lbm_steps_per_launch): 0 where the grid is
                             large enough for it to pay, 1 wherever the layout allows, -1 never */
+  int32_t walls;         /* 0: doubly periodic. 1: the columns x = 0 and x = nx - 1 are solid
+                            nodes with fullway bounce-back (the isothermal shocktube, Sec. 5):
+                            instead of colliding, a wall node sends each population back the way
+                            it came, so the wall lies halfway to the first fluid node and the fluid
+                            is x = 1 .. nx - 2 (y stays periodic). Requires nx >= 3
+                            (INVALID_ARGUMENT); the AA pattern and record_steps > 0 give
+                            LBM_ERR_UNSUPPORTED. lbm_moments and lbm_invariants include the wall
+                            nodes (their populations are part of the conserved total). */
 } lbm_params;
 
 typedef struct lbm_ctx lbm_ctx; /* opaque host-side context */
@@ -147,12 +155,12 @@ int64_t lbm_time(const lbm_ctx* ctx);
 
 /* Time steps one kernel launch of lbm_step advances for this context: 2 where the two-step
  * LDS-staged kernel applies, else 1 (-1 for a NULL context). It applies to the A-B pattern
- * with FP32 or FP64 storage, nx a multiple of 512, more than 2^15 storage positions and
- * two_step >= 0; with two_step = 0 also only where the grid gives at least three quarters
- * of the device's compute units a block of 2 or more rows x 512 columns (roughly
- * (nx/512) floor(ny/2) >= 3 CUs/4), below which the single-step kernel is faster. A pair of steps never
- * passes over a checkpoint time of a recorded run. Results do not depend on it: two steps
- * in one launch are bit-identical to two single steps. */
+ * with FP32 or FP64 storage, no walls, nx a multiple of 512, more than 2^15 storage
+ * positions and two_step >= 0; with two_step = 0 also only where the grid gives at least
+ * three quarters of the device's compute units a block of 2 or more rows x 512 columns
+ * (roughly (nx/512) floor(ny/2) >= 3 CUs/4), below which the single-step kernel is faster.
+ * A pair of steps never passes over a checkpoint time of a recorded run. Results do not
+ * depend on it: two steps in one launch are bit-identical to two single steps. */
 int32_t lbm_steps_per_launch(const lbm_ctx* ctx);
 
 const char* lbm_status_string(lbm_status s);

@@ -26,7 +26,7 @@ class lbm_params(ctypes.Structure):
         ("theta", ctypes.c_double), ("nu", ctypes.c_double), ("rho0", ctypes.c_double),
         ("model", ctypes.c_int32), ("storage", ctypes.c_int32), ("pattern", ctypes.c_int32),
         ("ckpt_stride", ctypes.c_int32), ("record_steps", ctypes.c_int64),
-        ("two_step", ctypes.c_int32),
+        ("two_step", ctypes.c_int32), ("walls", ctypes.c_int32),
     ]
 
 
@@ -95,12 +95,12 @@ def check(status, where):
 
 
 def make_params(nx, ny, theta, nu, rho0=1.0, model="complete", storage="f32", pattern="ab",
-                record_steps=0, ckpt_stride=0, two_step=0):
+                record_steps=0, ckpt_stride=0, two_step=0, walls=False):
     return lbm_params(int(nx), int(ny), float(theta), float(nu), float(rho0),
                       MODELS[model] if isinstance(model, str) else int(model),
                       DTYPES[storage] if isinstance(storage, str) else int(storage),
                       PATTERNS[pattern] if isinstance(pattern, str) else int(pattern),
-                      int(ckpt_stride), int(record_steps), int(two_step))
+                      int(ckpt_stride), int(record_steps), int(two_step), int(bool(walls)))
 
 
 # Thin wrappers with the C names (raw status returned; pointers as ints or None).

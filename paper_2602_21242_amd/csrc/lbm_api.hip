@@ -66,6 +66,12 @@ lbm_status validate(const lbm_params* p) {
   if (p->record_steps < 0) return fail(LBM_ERR_INVALID_ARGUMENT, "record_steps must be >= 0");
   if (p->ckpt_stride < 0) return fail(LBM_ERR_INVALID_ARGUMENT, "ckpt_stride must be >= 0");
   if (p->two_step < -1 || p->two_step > 1) return fail(LBM_ERR_INVALID_ARGUMENT, "two_step must be -1, 0 or 1");
+  if (p->walls != 0 && p->walls != 1) return fail(LBM_ERR_INVALID_ARGUMENT, "walls must be 0 or 1");
+  if (p->walls) {
+    if (p->nx < 3) return fail(LBM_ERR_INVALID_ARGUMENT, "walls need nx >= 3");
+    if (p->pattern != LBM_AB) return fail(LBM_ERR_UNSUPPORTED, "walls are implemented for the A-B pattern only");
+    if (p->record_steps > 0) return fail(LBM_ERR_UNSUPPORTED, "walls are not implemented for recorded (adjoint) runs");
+  }
   return LBM_OK;
 }
 
@@ -392,7 +398,8 @@ lbm_status lbm_init(const lbm_params* p, void* d_workspace, size_t workspace_byt
     d.rho0 = p->rho0;
     d.tau = p->nu / p->theta + 0.5;  // nu = theta (tau - 1/2)
     d.model = p->model;
-    d.fuse_rb = (p->pattern == LBM_AB && p->two_step >= 0)
+    d.walls = p->walls;
+    d.fuse_rb = (p->pattern == LBM_AB && p->two_step >= 0 && !p->walls)
                     ? dispatch_int(p->storage, [&](auto eng) { return decltype(eng)::fuse_row_blocks(d, p->two_step); })
                     : 0;
     c->time = 0;

@@ -21,6 +21,7 @@ struct RunDesc {
   double theta, nu, rho0, tau;
   int model;         // M_BGK ... M_COMPLETE
   int fuse_rb;       // row blocks of the two-step kernel; 0: one step per launch
+  int walls;         // 1: solid bounce-back columns at x = 0 and x = nx - 1 (A-B only)
 };
 
 // State layout at a given time: f_i(x) = buf[swap ? opp(i) : i][x - shift c_i].

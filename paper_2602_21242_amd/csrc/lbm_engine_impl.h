@@ -315,8 +315,26 @@ hipError_t launch_step_m(const RunDesc& d, int phase, const void* src, void* dst
   return launch_step_n<S, MODEL, 1>(d, phase, src, dst, rec, st);
 }
 
+template <class S, int MODEL>
+hipError_t launch_step_walls(const RunDesc& d, const void* src, void* dst, hipStream_t st) {
+  using T = typename StorageTraits<S>::T;
+  const Geo g = make_geo(d, 1);
+  hipLaunchKernelGGL((k_step_walls<S, MODEL>), step_grid(g), dim3(kBlock), 0, st, static_cast<const S*>(src),
+                     static_cast<S*>(dst), g, make_coef<T>(d));
+  return hipGetLastError();
+}
+
 template <class S>
 hipError_t Engine<S>::step(const RunDesc& d, int phase, const void* src, void* dst, void* rec, hipStream_t st) {
+  if (d.walls) {
+    if (phase != PH_AB || rec) return hipErrorInvalidValue;
+    switch (d.model) {
+      case M_BGK: return launch_step_walls<S, M_BGK>(d, src, dst, st);
+      case M_UC: return launch_step_walls<S, M_UC>(d, src, dst, st);
+      case M_PARTIAL: return launch_step_walls<S, M_PARTIAL>(d, src, dst, st);
+      default: return launch_step_walls<S, M_COMPLETE>(d, src, dst, st);
+    }
+  }
   switch (d.model) {
     case M_BGK: return launch_step_m<S, M_BGK>(d, phase, src, dst, rec, st);
     case M_UC: return launch_step_m<S, M_UC>(d, phase, src, dst, rec, st);

@@ -313,6 +313,42 @@ k_step2(const S* __restrict__ src, S* __restrict__ dst, Geo geo, Coef<typename S
   }
 }
 
+// One A-B time step with solid columns at x = 0 and x = nx - 1 (fullway bounce-back, the
+// isothermal shocktube of Sec. 5): a wall node pulls its populations like any node and,
+// instead of colliding, sends each back the way it came, g*_i = g_opp(i) (exact in the
+// shifted storage since w_i = w_opp(i)); fluid nodes collide as in k_step. One node per
+// thread, no padding access; used only for wall runs, which are small.
+template <class S, int MODEL>
+__global__ void __launch_bounds__(kBlock)
+k_step_walls(const S* __restrict__ src, S* __restrict__ dst, Geo geo, Coef<typename StorageTraits<S>::T> k) {
+  using T = typename StorageTraits<S>::T;
+  using Tr = StorageTraits<S>;
+  int y, lane;
+  const int s0 = first_group<1>(y, lane);
+  RowPos rp;
+  if (y >= geo.ny || !node_pos(geo, s0, lane, rp)) return;
+  const int x = lane * geo.S + s0;
+  const int ym = (y == 0) ? geo.ny - 1 : y - 1;
+  const int yp = (y == geo.ny - 1) ? 0 : y + 1;
+  const size_t rsb = size_t(geo.rs) * sizeof(S), psb = size_t(geo.ps) * sizeof(S);
+  const char* sr[3] = {reinterpret_cast<const char*>(src) + ym * rsb, reinterpret_cast<const char*>(src) + y * rsb,
+                       reinterpret_cast<const char*>(src) + yp * rsb};
+  T g[Q], out[Q];
+  static_for<0, Q>([&](auto I) {
+    constexpr int i = decltype(I)::value;
+    g[i] = Tr::load(ld1(at<S>(sr[-cy(i) + 1] + i * psb, rp.template of<-cx(i)>())));
+  });
+  if (x == 0 || x == geo.nx - 1) {
+#pragma unroll
+    for (int i = 0; i < Q; ++i) out[i] = g[opp(i)];
+  } else {
+    collide<T, MODEL>(g, out, k, nullptr);
+  }
+  char* orow = reinterpret_cast<char*>(dst) + y * rsb;
+#pragma unroll
+  for (int i = 0; i < Q; ++i) st1(at<S>(orow + i * psb, rp.p0), Tr::store(out[i]));
+}
+
 // One reverse step of the discrete adjoint: fbar^n(x) = J(m^n(x))^T fbar*(x) with the
 // reverse-streamed fbar*_i(x) = fbar^{n+1}_i(x + c_i). fbar uses the population layout in
 // the compute type (geo describes it); rec holds the step's recorded moments.

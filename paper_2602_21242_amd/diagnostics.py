@@ -6,6 +6,8 @@
   u_x = u_y = U/sqrt(2) + A sin(2 pi (-x + y)/n), wave vector k = (2 pi/n)(-1, 1),
   perturbation along (1, 1), so the mean flow U (along (1, 1)) advects the wave parallel
   to its crests;
+* the isothermal shocktube of the paper's second benchmark (Sec. 5) between two bounce-back
+  walls, against the exact solution of the isothermal Riemann problem;
 * vorticity, the vorticity thickness of the x-averaged profile and a count of vortex cores
   for the double shear layer of the paper's third benchmark (Sec. 5).
 
@@ -70,6 +72,70 @@ def rotated_wave_viscosity(model, theta, nu, mach, n=200, A=1e-3, skip=200, step
     if abs(a1) == 0 or abs(a1) > abs(a0) or dev > 1.5 * A:
         return None
     return decay_viscosity(a0, a1, 2.0 * (2.0 * math.pi / n) ** 2, steps) / nu
+
+
+def isothermal_riemann(x, t, x0, rho_l, rho_r, c):
+    """Exact solution of the isothermal Euler equations (sound speed c) for a fluid at rest
+    with density rho_l left of x0 and rho_r < rho_l right of it, at positions x (tensor) and
+    time t > 0: a left rarefaction along which u + c ln rho is constant, a plateau
+    (rho_m, u_m), and a shock whose jump conditions give u_m = c (rho_m - rho_r) /
+    sqrt(rho_m rho_r). Returns (rho, u, rho_m, u_m, shock speed); rho_m by bisection."""
+    if not (rho_l > rho_r > 0 and t > 0):
+        raise ValueError("need rho_l > rho_r > 0 and t > 0")
+    lo, hi = rho_r, rho_l
+    for _ in range(200):
+        mid = 0.5 * (lo + hi)
+        if math.log(rho_l / mid) > (mid - rho_r) / math.sqrt(mid * rho_r):
+            lo = mid
+        else:
+            hi = mid
+    rho_m = 0.5 * (lo + hi)
+    u_m = c * math.log(rho_l / rho_m)
+    s = rho_m * u_m / (rho_m - rho_r)
+    xi = (x.double() - x0) / t
+    fan = (xi >= -c) & (xi < u_m - c)
+    plateau = (xi >= u_m - c) & (xi < s)
+    rho = torch.where(xi < -c, torch.full_like(xi, rho_l), torch.full_like(xi, rho_r))
+    rho = torch.where(fan, rho_l * torch.exp(-(xi + c) / c), rho)
+    rho = torch.where(plateau, torch.full_like(xi, rho_m), rho)
+    u = torch.where(fan, xi + c, torch.zeros_like(xi))
+    u = torch.where(plateau, torch.full_like(xi, u_m), u)
+    return rho, u, rho_m, u_m, s
+
+
+def shocktube_run(model, theta, nu, nx=800, steps=400, rho_l=1.0, rho_r=0.5, storage="f64"):
+    """The isothermal shocktube of the paper's second benchmark: an nx x 1 box whose columns
+    x = 0 and nx - 1 are bounce-back walls, fluid at rest with rho = rho_l for x < nx/2 and
+    rho_r beyond, run for `steps` steps. Returns a dict with the fluid profiles (x = 1 ..
+    nx - 2), `stable` (finite, 0 < rho < 2 rho_l and |u| < 2 sqrt(theta) everywhere) and, when
+    stable: the plateau density and velocity (mean of the 21 nodes around
+    the middle of the exact plateau) and their errors relative to the exact solution
+    (sound speed sqrt(theta), jump at x = nx/2 - 1/2), the mean absolute density error over
+    the fluid, and the total variation of the density relative to the exact one (spurious
+    oscillations raise it above 1)."""
+    dev = torch.device("cuda", torch.cuda.current_device())
+    x = torch.arange(nx, device=dev, dtype=torch.float64)[None, :]
+    rho0 = torch.where(x < nx // 2, rho_l, rho_r).double()
+    sim = Simulation(nx, 1, theta, nu, 0.0 * x, 0.0 * x, rho=rho0, model=model, storage=storage, walls=True)
+    sim.step(steps)
+    r, u, _ = sim.moments()
+    sim.close()
+    r, u = r[0, 1:-1].double(), u[0, 1:-1].double()
+    xf = x[0, 1:-1]
+    c = math.sqrt(theta)
+    stable = bool(torch.isfinite(r).all() and torch.isfinite(u).all())
+    stable = stable and bool(((r > 0) & (r < 2 * rho_l) & (u.abs() < 2 * c)).all())
+    out = {"steps": steps, "rho": r, "u": u, "stable": stable}
+    re, ue, rho_m, u_m, s = isothermal_riemann(xf, float(steps), nx / 2 - 0.5, rho_l, rho_r, c)
+    out.update(rho_exact=re, u_exact=ue, rho_plateau_exact=rho_m, u_plateau_exact=u_m)
+    if out["stable"]:
+        xm = int(round(nx / 2 - 0.5 + steps * 0.5 * (u_m - c + s))) - 1  # index into the fluid
+        pl = slice(xm - 10, xm + 11)
+        rp, up = float(r[pl].mean()), float(u[pl].mean())
+        tv = float((r[1:] - r[:-1]).abs().sum()) / float((re[1:] - re[:-1]).abs().sum())
+        out.update(rho_plateau=rp, u_plateau=up, rho_plateau_err=rp / rho_m - 1, u_plateau_err=up / u_m - 1,
+                   l1_rho=float((r - re).abs().mean()), tv_ratio=tv)
+    return out
 
 
 def vorticity(ux, uy):

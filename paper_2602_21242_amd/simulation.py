@@ -20,13 +20,14 @@ class Simulation:
     pattern: "ab" | "aa". record_steps > 0 checkpoints the first record_steps steps for
     adjoint() (sqrt(N) checkpoints by default, or every ckpt_stride steps). two_step: 0 runs
     two steps per launch where the grid is large enough for it to pay, 1 wherever the layout
-    allows, -1 never (results are bit-identical).
+    allows, -1 never (results are bit-identical). walls: solid bounce-back columns at x = 0
+    and x = nx - 1 (A-B pattern, no recording).
     """
 
     def __init__(self, nx, ny, theta, nu, ux, uy, rho=None, rho0=1.0, model="complete", storage="f32",
-                 pattern="ab", record_steps=0, ckpt_stride=0, two_step=0, device=None):
+                 pattern="ab", record_steps=0, ckpt_stride=0, two_step=0, walls=False, device=None):
         self.params = capi.make_params(nx, ny, theta, nu, rho0, model, storage, pattern, record_steps, ckpt_stride,
-                                       two_step)
+                                       two_step, walls)
         self.device = torch.device(device) if device is not None else torch.device("cuda", torch.cuda.current_device())
         s, nbytes = capi.lbm_workspace_bytes(self.params)
         capi.check(s, "lbm_workspace_bytes")

@@ -77,6 +77,7 @@ def test_workspace_plan(capi, storage, esize, tsize, pattern, nbuf):
 BAD = [dict(nx=0), dict(ny=0), dict(nx=-3), dict(theta=0.0), dict(theta=1.0), dict(theta=float("nan")),
        dict(nu=0.0), dict(nu=-1e-3), dict(nu=float("inf")), dict(rho0=0.0), dict(model=4), dict(model=-1),
        dict(storage=4), dict(pattern=2), dict(record_steps=-1), dict(ckpt_stride=-2), dict(two_step=2), dict(two_step=-2),
+       dict(walls=True, nx=2),
        dict(nx=65536, ny=32768), dict(nx=65537, ny=32767), dict(nx=2 ** 31 - 63, ny=1)]
 
 
@@ -134,3 +135,18 @@ def test_bench_refuses_more_than_one_gpu():
                        text=True, timeout=120)
     assert r.returncode == 2
     assert "one GPU" in r.stderr
+
+
+def test_wall_parameters(capi):
+    """walls: 0 or 1 (else invalid); nx >= 3; A-B without recording (else unsupported); the
+    workspace does not depend on it."""
+    s0, n0 = capi.lbm_workspace_bytes(_params(capi))
+    s1, n1 = capi.lbm_workspace_bytes(_params(capi, walls=True))
+    assert s0 == s1 == capi.LBM_OK and n0 == n1
+    p = _params(capi)
+    p.walls = 2
+    assert capi.lbm_workspace_bytes(p)[0] == capi.LBM_ERR_INVALID_ARGUMENT
+    s, _ = capi.lbm_workspace_bytes(_params(capi, walls=True, pattern="aa"))
+    assert s == capi.LBM_ERR_UNSUPPORTED and "A-B" in capi.last_error()
+    s, _ = capi.lbm_workspace_bytes(_params(capi, walls=True, record_steps=5))
+    assert s == capi.LBM_ERR_UNSUPPORTED and "recorded" in capi.last_error()

@@ -78,3 +78,15 @@ def test_isothermal_riemann_solution_satisfies_jump_conditions(c):
     mass = np.trapezoid(rho, x)
     assert abs(mass - (rl * 399.5 + rr * 400.5)) <= 1e-3
     assert rho[0] == rl and rho[-1] == rr and u[0] == 0.0 and u[-1] == 0.0
+
+
+@pytest.mark.parametrize("c", [math.sqrt(0.4), math.sqrt(0.55)])
+def test_package_riemann_solution_matches_test_side(c):
+    """The package's exact shocktube solution (torch) against the test-side one (numpy)."""
+    from tests.lbm_diag import isothermal_riemann
+    x = np.arange(800, dtype=np.float64)
+    r0, u0, rm0, um0, s0 = isothermal_riemann(x, 400.0, 399.5, 1.0, 0.5, c)
+    r1, u1, rm1, um1, s1 = d.isothermal_riemann(torch.from_numpy(x), 400.0, 399.5, 1.0, 0.5, c)
+    assert abs(rm1 - rm0) <= 1e-14 and abs(um1 - um0) <= 1e-14 and abs(s1 - s0) <= 1e-14
+    np.testing.assert_allclose(r1.numpy(), r0, rtol=1e-14, atol=0)
+    np.testing.assert_allclose(u1.numpy(), u0, rtol=0, atol=1e-15)
