@@ -313,17 +313,24 @@ lbm_status sweep(lbm_ctx* c, int* out_b) {
                                      : do_step(c, c->rec_slot(j));
       if (st != LBM_OK) return st;
     }
-    for (int64_t t = t1 - 1; t >= t0; --t) {
+    // Reverse steps t = t1 - 1 .. t0, two per launch (t and t - 1) where the two-step adjoint
+    // kernel applies.
+    for (int64_t t = t1 - 1; t >= t0;) {
+      const bool pair = c->d.adj_rb > 0 && t - 1 >= t0;
       st = dispatch(c->p.storage, [&](auto eng) -> lbm_status {
         using E = decltype(eng);
         using T = typename E::T;
-        hipError_t e = E::adjoint_step(c->d, static_cast<const T*>(c->fbar(b)), static_cast<T*>(c->fbar(1 - b)),
-                                       static_cast<const T*>(c->rec_slot(t - t0)), c->stream);
+        const T* in = static_cast<const T*>(c->fbar(b));
+        T* out = static_cast<T*>(c->fbar(1 - b));
+        hipError_t e = pair ? E::adjoint_step2(c->d, in, out, static_cast<const T*>(c->rec_slot(t - t0)),
+                                               static_cast<const T*>(c->rec_slot(t - 1 - t0)), c->stream)
+                            : E::adjoint_step(c->d, in, out, static_cast<const T*>(c->rec_slot(t - t0)), c->stream);
         if (e != hipSuccess) return fail(LBM_ERR_HIP, std::string("adjoint kernel launch: ") + hipGetErrorString(e));
         return LBM_OK;
       });
       if (st != LBM_OK) return st;
       b ^= 1;
+      t -= pair ? 2 : 1;
     }
   }
   *out_b = b;
@@ -402,6 +409,9 @@ lbm_status lbm_init(const lbm_params* p, void* d_workspace, size_t workspace_byt
     d.fuse_rb = (p->pattern == LBM_AB && p->two_step >= 0 && !p->walls)
                     ? dispatch_int(p->storage, [&](auto eng) { return decltype(eng)::fuse_row_blocks(d, p->two_step); })
                     : 0;
+    d.adj_rb = (p->record_steps > 0 && p->two_step >= 0)
+                   ? dispatch_int(p->storage, [&](auto eng) { return decltype(eng)::adjoint_row_blocks(d, p->two_step); })
+                   : 0;
     c->time = 0;
     c->cur = 0;
     c->rec_valid = p->record_steps > 0;

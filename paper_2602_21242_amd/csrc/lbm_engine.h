@@ -21,6 +21,7 @@ struct RunDesc {
   double theta, nu, rho0, tau;
   int model;         // M_BGK ... M_COMPLETE
   int fuse_rb;       // row blocks of the two-step kernel; 0: one step per launch
+  int adj_rb;        // row blocks of the two-step adjoint kernel; 0: one reverse step per launch
   int walls;         // 1: solid bounce-back columns at x = 0 and x = nx - 1 (A-B only)
 };
 
@@ -40,6 +41,7 @@ struct Engine {
   // blocks for the current device (mode 0: only where it pays, 1: wherever the layout and
   // the storage type allow it), or 0 for one step per launch.
   static int fuse_row_blocks(const RunDesc& d, int mode);
+  static int adjoint_row_blocks(const RunDesc& d, int mode);
   static hipError_t step2(const RunDesc& d, const void* src, void* dst, void* rec1, void* rec2, hipStream_t st);
   static hipError_t init(const RunDesc& d, LayoutSel L, void* buf, const double* rho, const double* ux,
                          const double* uy, hipStream_t st);
@@ -54,6 +56,10 @@ struct Engine {
   static hipError_t fbar_import(const RunDesc& d, const T* dense, T* fbar, hipStream_t st);
   static hipError_t fbar_export(const RunDesc& d, const T* fbar, T* dense, hipStream_t st);
   static hipError_t adjoint_step(const RunDesc& d, const T* fbar_next, T* fbar, const T* rec, hipStream_t st);
+  // Two reverse steps (fbar^{n+1} -> fbar^{n-1}) over d.adj_rb row blocks; rec_hi holds the
+  // records of step n, rec_lo those of step n - 1.
+  static hipError_t adjoint_step2(const RunDesc& d, const T* fbar_next, T* fbar, const T* rec_hi, const T* rec_lo,
+                                  hipStream_t st);
   static hipError_t ic_adjoint(const RunDesc& d, LayoutSel L, const void* buf0, const T* fbar, T* uxb, T* uyb,
                                hipStream_t st);
 };

@@ -377,9 +377,9 @@ template <> struct FuseSteps<double> { static constexpr bool value = true; };
 // the largest row-block count that keeps it needs checking. On MI355X this ranking matched
 // the measured throughput of every candidate tried on 512^2 to 4096^2 grids. In mode 0 a
 // grid that cannot give three quarters of the compute units a block keeps single steps.
-template <class S>
-int Engine<S>::fuse_row_blocks(const RunDesc& d, int mode) {
-  if (!FuseSteps<S>::value || d.nx % kLanes != 0 || (d.pitch / kLanes) % kFuseGroups != 0) return 0;
+// The two-step adjoint kernel has the same block structure and uses the same plan.
+inline int plan_row_blocks(const RunDesc& d, int mode) {
+  if (d.nx % kLanes != 0 || (d.pitch / kLanes) % kFuseGroups != 0) return 0;
   int dev = 0, cus = 0;
   if (hipGetDevice(&dev) != hipSuccess ||
       hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus < 1)
@@ -399,6 +399,16 @@ int Engine<S>::fuse_row_blocks(const RunDesc& d, int mode) {
   }
   if (mode == 0 && 4 * cols * best < 3L * cus) return 0;
   return int(best);
+}
+
+template <class S>
+int Engine<S>::fuse_row_blocks(const RunDesc& d, int mode) {
+  return FuseSteps<S>::value ? plan_row_blocks(d, mode) : 0;
+}
+
+template <class S>
+int Engine<S>::adjoint_row_blocks(const RunDesc& d, int mode) {
+  return plan_row_blocks(d, mode);
 }
 
 template <class S>
@@ -477,6 +487,22 @@ hipError_t Engine<S>::fbar_import(const RunDesc& d, const T* dense, T* fbar, hip
 template <class S>
 hipError_t Engine<S>::fbar_export(const RunDesc& d, const T* fbar, T* dense, hipStream_t st) {
   hipLaunchKernelGGL(k_fbar_export<T>, dim3(node_blocks(d)), dim3(kBlock), 0, st, d, fbar, dense);
+  return hipGetLastError();
+}
+
+template <class S>
+hipError_t Engine<S>::adjoint_step2(const RunDesc& d, const T* fbar_next, T* fbar, const T* rec_hi, const T* rec_lo,
+                                    hipStream_t st) {
+  if (d.adj_rb < 1 || d.adj_rb > d.ny) return hipErrorInvalidValue;
+  const Geo g = make_geo(d, 1);
+  const Coef<T> k = make_coef<T>(d);
+  const dim3 grid(unsigned(g.S / kFuseGroups), unsigned(d.adj_rb)), block((kFuseGroups + 2) * kLanes);
+  switch (d.model) {
+    case M_BGK: hipLaunchKernelGGL((k_adjoint_step2<T, M_BGK>), grid, block, 0, st, fbar_next, fbar, g, k, rec_hi, rec_lo, d.rs_rec); break;
+    case M_UC: hipLaunchKernelGGL((k_adjoint_step2<T, M_UC>), grid, block, 0, st, fbar_next, fbar, g, k, rec_hi, rec_lo, d.rs_rec); break;
+    case M_PARTIAL: hipLaunchKernelGGL((k_adjoint_step2<T, M_PARTIAL>), grid, block, 0, st, fbar_next, fbar, g, k, rec_hi, rec_lo, d.rs_rec); break;
+    default: hipLaunchKernelGGL((k_adjoint_step2<T, M_COMPLETE>), grid, block, 0, st, fbar_next, fbar, g, k, rec_hi, rec_lo, d.rs_rec); break;
+  }
   return hipGetLastError();
 }
 

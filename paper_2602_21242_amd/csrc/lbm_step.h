@@ -313,6 +313,94 @@ k_step2(const S* __restrict__ src, S* __restrict__ dst, Geo geo, Coef<typename S
   }
 }
 
+// Two reverse steps per launch, staged through LDS like k_step2 (same blocks, halo
+// wavefronts, XCD-aware tile order and three-row ring). Phase A computes fbar^n of every
+// wavefront's node at row r from fbar^{n+1} gathered at x + c_i and the records rec_hi of
+// step n; phase B computes fbar^{n-1} of row r - 1 for the interior wavefronts from the
+// ring and the records rec_lo of step n - 1, and stores it. The same operations in the same
+// order as two k_adjoint_step launches, so the result is bit-identical. fbar uses the
+// population layout in the compute type; requires nx % 64 == 0 and S % kFuseGroups == 0.
+template <class T>
+__device__ __forceinline__ void load_gathered(const T* src, const Geo& geo, int r, const RowPos& rp, T fs[Q]) {
+  const int y = r < 0 ? r + geo.ny : (r >= geo.ny ? r - geo.ny : r);
+  const int ym = (y == 0) ? geo.ny - 1 : y - 1;
+  const int yp = (y == geo.ny - 1) ? 0 : y + 1;
+  const size_t rsb = size_t(geo.rs) * sizeof(T), psb = size_t(geo.ps) * sizeof(T);
+  const char* sr[3] = {reinterpret_cast<const char*>(src) + ym * rsb, reinterpret_cast<const char*>(src) + y * rsb,
+                       reinterpret_cast<const char*>(src) + yp * rsb};
+  static_for<0, Q>([&](auto I) {
+    constexpr int i = decltype(I)::value;
+    fs[i] = ld1(at<T>(sr[cy(i) + 1] + i * psb, rp.template of<cx(i)>()));
+  });
+}
+
+template <class T>
+__device__ __forceinline__ void load_record(const T* rec, const Geo& geo, int64_t rec_rs, int r, int pos, T rv[NREC]) {
+  const int y = r < 0 ? r + geo.ny : (r >= geo.ny ? r - geo.ny : r);
+  const char* rrow = reinterpret_cast<const char*>(rec) + y * (size_t(rec_rs) * sizeof(T));
+#pragma unroll
+  for (int j = 0; j < NREC; ++j) rv[j] = ld1(at<T>(rrow + j * size_t(geo.ps) * sizeof(T), pos));
+}
+
+template <class T, int MODEL>
+__global__ void __launch_bounds__((kFuseGroups + 2) * kLanes)
+k_adjoint_step2(const T* __restrict__ fbar_next, T* __restrict__ fbar, Geo geo, Coef<T> k,
+                const T* __restrict__ rec_hi, const T* __restrict__ rec_lo, int64_t rec_rs) {
+  constexpr int G = kFuseGroups;
+  __shared__ T ring[3][G + 2][Q][kLanes];
+  const int w = __builtin_amdgcn_readfirstlane(int(threadIdx.x / kLanes));
+  const int lane = int(threadIdx.x % kLanes);
+  int bx, by;
+  xcd_tile(bx, by);
+  const int s0 = bx * G;
+  const int y0 = int(int64_t(by) * geo.ny / gridDim.y);
+  const int y1 = int(int64_t(by + 1) * geo.ny / gridDim.y);
+  RowPos ra;
+  if (w == 0 || w == G + 1) {
+    RowPos e;
+    node_pos(geo, w == 0 ? s0 : s0 + G - 1, lane, e);
+    const int p = w == 0 ? e.pm : e.pp;
+    node_pos(geo, p / kLanes, p % kLanes, ra);
+  } else {
+    node_pos(geo, s0 + w - 1, lane, ra);
+  }
+  const bool interior = w >= 1 && w <= G;
+  const int pb = (s0 + w - 1) * kLanes + lane;
+  const size_t rsb = size_t(geo.rs) * sizeof(T), psb = size_t(geo.ps) * sizeof(T);
+
+  T fs[Q], rv[NREC];
+  load_gathered<T>(fbar_next, geo, y0 - 1, ra, fs);
+  load_record<T>(rec_hi, geo, rec_rs, y0 - 1, ra.p0, rv);
+  for (int r = y0 - 1; r <= y1; ++r) {
+    const int slot = (r - y0 + 1) % 3;
+    {
+      T fb[Q];
+      collide_vjp<T, MODEL>(fs, rv, k, fb);
+#pragma unroll
+      for (int i = 0; i < Q; ++i) ring[slot][w][i][lane] = fb[i];
+    }
+    if (r < y1) {
+      load_gathered<T>(fbar_next, geo, r + 1, ra, fs);
+      load_record<T>(rec_hi, geo, rec_rs, r + 1, ra.p0, rv);
+    }
+    __syncthreads();
+    if (interior && r > y0) {
+      const int yr = r - 1;
+      T g[Q], fb[Q], rl[NREC];
+      load_record<T>(rec_lo, geo, rec_rs, yr, pb, rl);
+      static_for<0, Q>([&](auto I) {
+        constexpr int i = decltype(I)::value;
+        g[i] = ring[(yr + cy(i) - y0 + 1) % 3][w + cx(i)][i][lane];
+      });
+      collide_vjp<T, MODEL>(g, rl, k, fb);
+      char* orow = reinterpret_cast<char*>(fbar) + yr * rsb;
+#pragma unroll
+      for (int i = 0; i < Q; ++i) st1(at<T>(orow + i * psb, pb), fb[i]);
+    }
+    __syncthreads();
+  }
+}
+
 // One A-B time step with solid columns at x = 0 and x = nx - 1 (fullway bounce-back, the
 // isothermal shocktube of Sec. 5): a wall node pulls its populations like any node and,
 // instead of colliding, sends each back the way it came, g*_i = g_opp(i) (exact in the

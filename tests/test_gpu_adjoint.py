@@ -45,28 +45,38 @@ def test_population_adjoint_fp64(model, pattern):
         assert err <= 1e-12, (stride, err)
 
 
-@pytest.mark.parametrize("model", ["bgk", "complete"])
-@pytest.mark.parametrize("storage", ["f64", "f32"])
+@pytest.mark.parametrize("model", ["bgk", "uc", "complete"])
+@pytest.mark.parametrize("storage", ["f64", "f32", "f16"])
 def test_population_adjoint_with_two_step_launches(model, storage):
-    """With the two-step kernel asked for (512 x 100, two_step = 1), the recorded forward run and
-    the recomputation in the reverse sweep take two steps per launch (with moment records of
-    both), except where a pair would pass over a checkpoint time. N = 7 with spacings 3
-    (segments of 3, 3, 1 steps; the forward pair from step 2 would skip checkpoint 3), 2 and
-    the default: against the oracle's complex-step adjoint."""
+    """With two steps per launch asked for (512 x 100, two_step = 1) the recorded forward run
+    and the recomputation in the reverse sweep take two steps per launch (FP32/FP64 storage;
+    with moment records of both, except where a pair would pass over a checkpoint time), and
+    the reverse sweep takes two adjoint steps per launch (every storage type; the adjoint
+    computes in FP32 or FP64), except for a segment's last odd step. N = 7 with spacings 3
+    (segments of 3, 3, 1 steps), 2 and the default: against the same run with two_step = -1
+    (one step per launch everywhere) to rounding (the two adjoint kernels inline the same
+    VJP, but the compiler may contract its products into FMAs differently: 1e-14 of the
+    largest entry in FP64, 1e-6 in FP32), and for FP64/FP32 against the oracle's
+    complex-step adjoint."""
     import torch
     nx, ny, th, nu, N = 512, 100, 0.4, 0.02, 7
     f0 = inp.random_populations(nx, ny, seed=27, amp=0.05)
     w = inp.random_direction((9, ny, nx), seed=28)
-    ref = _oracle_population_adjoint(f0, w, th, nu, model, N)
+    ref = _oracle_population_adjoint(f0, w, th, nu, model, N) if storage != "f16" else None
     dtype = torch.float64 if storage == "f64" else torch.float32
     for stride in (3, 2, 0):
-        sim = gpu_sim(nx, ny, th, nu, model, storage, "ab", f0=f0, record_steps=N, ckpt_stride=stride,
-                      two_step=1)
-        assert sim.steps_per_launch == 2
-        sim.step(N)
-        got = sim.adjoint_populations(_t(w, dtype)).cpu().numpy()
-        err = np.max(np.abs(got - ref)) / np.max(np.abs(ref))
-        assert err <= (1e-12 if storage == "f64" else 1e-5), (stride, err)
+        got = {}
+        for ts in (1, -1):
+            sim = gpu_sim(nx, ny, th, nu, model, storage, "ab", f0=f0, record_steps=N, ckpt_stride=stride,
+                          two_step=ts)
+            assert sim.steps_per_launch == (2 if ts == 1 and storage != "f16" else 1)
+            sim.step(N)
+            got[ts] = sim.adjoint_populations(_t(w, dtype)).cpu().numpy()
+        scale = np.max(np.abs(got[-1]))
+        assert np.max(np.abs(got[1] - got[-1])) <= (1e-14 if storage == "f64" else 1e-6) * scale, stride
+        if ref is not None:
+            err = np.max(np.abs(got[1] - ref)) / np.max(np.abs(ref))
+            assert err <= (1e-12 if storage == "f64" else 1e-5), (stride, err)
 
 
 @pytest.mark.parametrize("model", MODELS)
