@@ -361,13 +361,21 @@ hipError_t launch_step2_m(const RunDesc& d, const void* src, void* dst, void* re
   return hipGetLastError();
 }
 
-// Storage types served by the two-step kernel. Measured on MI355X, complete model, GLUPS
-// single-step / two-step: FP32 89.7 / 134.5 (4096^2), FP64 42.0 / 71.4 (8192^2); the 16-bit
-// paths, whose single-step kernels are already limited by arithmetic rather than bandwidth,
-// lose (FP16 167 / 144, BF16 170 / 160).
-template <class S> struct FuseSteps { static constexpr bool value = false; };
-template <> struct FuseSteps<float> { static constexpr bool value = true; };
-template <> struct FuseSteps<double> { static constexpr bool value = true; };
+// Storage types and models served by the two-step kernel. Measured on MI355X (GLUPS,
+// single-step / two-step): complete model FP32 89.7 / 141 (4096^2), FP64 42.0 / 76
+// (8192^2); at 16-bit storage, where the OReg models' single-step kernels are already
+// limited by vector arithmetic, the halo recomputation makes two steps slower (complete
+// model, 8192^2: FP16 167 / 146, BF16 173 / 168), while LBGK's short collision leaves them
+// bandwidth-bound and two steps pay (FP16 179 / 181, BF16 179 / 222).
+template <class S> struct FuseSteps {
+  static constexpr bool value(int model) { return model == M_BGK; }
+};
+template <> struct FuseSteps<float> {
+  static constexpr bool value(int) { return true; }
+};
+template <> struct FuseSteps<double> {
+  static constexpr bool value(int) { return true; }
+};
 
 // Row blocks of the two-step kernel. A block of h rows computes h + 2 rows of step 1 and h
 // of step 2, and a compute unit works through its share of the blocks in turn, so a launch
@@ -403,7 +411,7 @@ inline int plan_row_blocks(const RunDesc& d, int mode) {
 
 template <class S>
 int Engine<S>::fuse_row_blocks(const RunDesc& d, int mode) {
-  return FuseSteps<S>::value ? plan_row_blocks(d, mode) : 0;
+  return FuseSteps<S>::value(d.model) ? plan_row_blocks(d, mode) : 0;
 }
 
 template <class S>
@@ -413,13 +421,17 @@ int Engine<S>::adjoint_row_blocks(const RunDesc& d, int mode) {
 
 template <class S>
 hipError_t Engine<S>::step2(const RunDesc& d, const void* src, void* dst, void* rec1, void* rec2, hipStream_t st) {
-  if (d.fuse_rb < 1 || d.fuse_rb > d.ny) return hipErrorInvalidValue;
-  switch (d.model) {
-    case M_BGK: return launch_step2_m<S, M_BGK>(d, src, dst, rec1, rec2, st);
-    case M_UC: return launch_step2_m<S, M_UC>(d, src, dst, rec1, rec2, st);
-    case M_PARTIAL: return launch_step2_m<S, M_PARTIAL>(d, src, dst, rec1, rec2, st);
-    default: return launch_step2_m<S, M_COMPLETE>(d, src, dst, rec1, rec2, st);
+  if (d.fuse_rb < 1 || d.fuse_rb > d.ny || !FuseSteps<S>::value(d.model)) return hipErrorInvalidValue;
+  if (d.model == M_BGK) return launch_step2_m<S, M_BGK>(d, src, dst, rec1, rec2, st);
+  // The OReg models are instantiated only for the storage types that use them.
+  if constexpr (FuseSteps<S>::value(M_COMPLETE)) {
+    switch (d.model) {
+      case M_UC: return launch_step2_m<S, M_UC>(d, src, dst, rec1, rec2, st);
+      case M_PARTIAL: return launch_step2_m<S, M_PARTIAL>(d, src, dst, rec1, rec2, st);
+      default: return launch_step2_m<S, M_COMPLETE>(d, src, dst, rec1, rec2, st);
+    }
   }
+  return hipErrorInvalidValue;
 }
 
 template <class S>
