@@ -223,118 +223,116 @@ __device__ __forceinline__ void collide(const T g[Q], T out[Q], const Coef<T>& k
 // Vector-Jacobian product of one node's collision: given fbs = dJ/df* (post-collision) and the
 // recorded moments (rho, ux, uy, N_xx, N_xy) of the pre-collision state, returns dJ/df.
 // The post-collision populations depend on the node's populations only through
-// m = (rho, j_x, j_y, D, P_xy) (and, for LBGK, directly), so dJ/df = M^T dJ/dm; dJ/dm is
-// accumulated here by reverse-mode differentiation of the steps of collide().
+// m = (rho, j_x, j_y, D, P_xy) (and, for LBGK, directly), so dJ/df = M^T dJ/dm. With the
+// populations indexed by (c_x, c_y) the equilibrium and the OReg population are sums of
+// products of a function of c_x and one of c_y (eq:guidedEq, eq:oreg), so every sum over i
+// of fbs_i times such a product is a 3 x 3 bilinear form x^T F y; dJ/d(rho, u, N) is a few
+// of those, and the corrections Psi (linear in f^OReg through psi and the prefactor) only
+// reweight F. Checked against the complex-step derivative of the literal collision.
 template <class T, int MODEL>
 __device__ __forceinline__ void collide_vjp(const T fbs[Q], const T rec[NREC], const Coef<T>& k, T fbar[Q]) {
   const T rho = rec[0], ux = rec[1], uy = rec[2], Nxx = rec[3], Nxy = rec[4];
   const T ux2 = ux * ux, uy2 = uy * uy;
-  const T hx0 = k.r0 - ux2, hxp = k.r1 + T(0.5) * (ux2 + ux), hxm = k.r1 + T(0.5) * (ux2 - ux);
-  const T hy0 = k.r0 - uy2, hyp = k.r1 + T(0.5) * (uy2 + uy), hym = k.r1 + T(0.5) * (uy2 - uy);
+  // Per-axis vectors over c = -1, 0, +1 (index c + 1): the GEq factors A0 = Phi(c, u_x) and
+  // their u-derivatives dA0, and for the OReg population A1 = A0 C, A2 = A0 C^2 with
+  // C = c - u_x, and their u_x-derivatives (dC/du_x = -1); B* likewise in y.
+  T A0[3], A1[3], A2[3], dA0[3], dA1[3], dA2[3];
+  T B0[3], B1[3], B2[3], dB0[3], dB1[3], dB2[3];
+  A0[0] = k.r1 + T(0.5) * (ux2 - ux), A0[1] = k.r0 - ux2, A0[2] = k.r1 + T(0.5) * (ux2 + ux);
+  B0[0] = k.r1 + T(0.5) * (uy2 - uy), B0[1] = k.r0 - uy2, B0[2] = k.r1 + T(0.5) * (uy2 + uy);
+  dA0[0] = ux - T(0.5), dA0[1] = T(-2) * ux, dA0[2] = ux + T(0.5);
+  dB0[0] = uy - T(0.5), dB0[1] = T(-2) * uy, dB0[2] = uy + T(0.5);
+  // F[a][b]: the reverse-streamed adjoint populations arranged by (c_x, c_y).
+  T F[3][3];
+#pragma unroll
+  for (int i = 0; i < Q; ++i) F[cx(i) + 1][cy(i) + 1] = fbs[i];
+  auto matvec = [](const T M[3][3], const T v[3], T out[3]) {
+#pragma unroll
+    for (int a = 0; a < 3; ++a) out[a] = M[a][0] * v[0] + M[a][1] * v[1] + M[a][2] * v[2];
+  };
+  auto dot = [](const T x[3], const T y[3]) { return x[0] * y[0] + x[1] * y[1] + x[2] * y[2]; };
 
-  T rhob = T(0), uxb = T(0), uyb = T(0), Nxxb = T(0), Nxyb = T(0);
-  T hxb0 = T(0), hxbp = T(0), hxbm = T(0), hyb0 = T(0), hybp = T(0), hybm = T(0);
-  T feqsb[Q], Pb[Q];
-  T direct[Q];
-
+  T uxb = T(0), uyb = T(0), Nxxb = T(0), Nxyb = T(0);
+  T direct_scale = T(0);  // LBGK: fbar gets omb fbs directly
+  T eq_scale = T(1);      // weight of fbs in the equilibrium part
   if (MODEL == M_BGK) {
-#pragma unroll
-    for (int i = 0; i < Q; ++i) {
-      direct[i] = k.omb * fbs[i];
-      feqsb[i] = (T(1) - k.omb) * fbs[i];
-      Pb[i] = T(0);
-    }
+    direct_scale = k.omb;
+    eq_scale = T(1) - k.omb;
   } else {
+    // Weights of the OReg population f^OReg_i = P_i t_i in the output: omb fbs, plus, for the
+    // corrected models, the chain through Psi, which depends on f^OReg via psi = sum c f^OReg
+    // and (complete model) the prefactor, a moment of f^OReg.
+    T W[3][3];
 #pragma unroll
-    for (int i = 0; i < Q; ++i) {
-      direct[i] = T(0);
-      feqsb[i] = fbs[i];
-    }
-    // Forward recomputation of the OReg quantities.
-    const T n1 = Nxx * k.inv2th2, n2 = Nxy * (T(2) * k.inv2th2);
-    const T Cxm = T(-1) - ux, Cx0 = -ux, Cxp = T(1) - ux;
-    const T Cym = T(-1) - uy, Cy0 = -uy, Cyp = T(1) - uy;
-    const T Sxm = Cxm * Cxm, Sx0 = Cx0 * Cx0, Sxp = Cxp * Cxp;
-    const T Sym = Cym * Cym, Sy0 = Cy0 * Cy0, Syp = Cyp * Cyp;
-    const T X1m = Sxm * n1, X10 = Sx0 * n1, X1p = Sxp * n1;
-    const T Y1m = Sym * n1, Y10 = Sy0 * n1, Y1p = Syp * n1;
-    const T Y2m = Cym * n2, Y20 = Cy0 * n2, Y2p = Cyp * n2;
-    T P[Q], t[Q], fo[Q];
+    for (int a = 0; a < 3; ++a)
 #pragma unroll
-    for (int i = 0; i < Q; ++i) {
-      P[i] = sel(cx(i), hxm, hx0, hxp) * sel(cy(i), hym, hy0, hyp);
-      t[i] = sel(cx(i), X1m, X10, X1p) - sel(cy(i), Y1m, Y10, Y1p) + sel(cx(i), Cxm, Cx0, Cxp) * sel(cy(i), Y2m, Y20, Y2p);
-      fo[i] = P[i] * t[i];
-    }
-    // out = feqs + omb (fo + Psi)
-    T fob[Q];
-#pragma unroll
-    for (int i = 0; i < Q; ++i) fob[i] = k.omb * fbs[i];
+      for (int b = 0; b < 3; ++b) W[a][b] = k.omb * F[a][b];
     if (MODEL == M_PARTIAL || MODEL == M_COMPLETE) {
-      T Psib[Q];
-#pragma unroll
-      for (int i = 0; i < Q; ++i) Psib[i] = k.omb * fbs[i];
-      const T psxb = T(0.5) * (Psib[3] - Psib[1]);
-      const T psyb = T(0.5) * (Psib[4] - Psib[2]);
+      // Psi bar = omb fbs; psi bar_x = (Psib_3 - Psib_1)/2, psi bar_y = (Psib_4 - Psib_2)/2.
+      const T psxb = T(0.5) * (W[0][1] - W[2][1]);
+      const T psyb = T(0.5) * (W[1][0] - W[1][2]);
       if (MODEL == M_COMPLETE) {
-        const T pf = -k.inv4th2 * ((fo[1] + fo[3]) - (fo[2] + fo[4]));
+        // Prefactor from its closed form (the moment of f^OReg), stress-error weights and
+        // their direct u-dependence; the prefactor's own dependence on f^OReg enters W.
+        const T pf = -k.inv4th2 * (Nxx * k.inv2th2) * (k.b0 + ux2 * (ux2 - T(1)) + uy2 * (uy2 - T(1)));
         const T ax = k.a0 + ux2 * (ux2 - T(1));
         const T ay = k.a0 + uy2 * (uy2 - T(1));
         const T bxy = ux * uy * (ux2 - uy2);
-        const T sb = (Psib[5] + Psib[6]) + (Psib[7] + Psib[8]);
-        const T Ptyyb = T(0.5) * (Psib[1] + Psib[3]) - T(0.25) * sb;
-        const T Ptxxb = T(0.5) * (Psib[2] + Psib[4]) - T(0.25) * sb;
-        const T Ptxyb = T(0.25) * ((Psib[6] + Psib[8]) - (Psib[5] + Psib[7]));
+        const T sb = (W[2][2] + W[0][2]) + (W[0][0] + W[2][0]);
+        const T Ptyyb = T(0.5) * (W[2][1] + W[0][1]) - T(0.25) * sb;
+        const T Ptxxb = T(0.5) * (W[1][2] + W[1][0]) - T(0.25) * sb;
+        const T Ptxyb = T(0.25) * ((W[0][2] + W[2][0]) - (W[2][2] + W[0][0]));
         const T pfb = -Ptxxb * ax + Ptyyb * ay + Ptxyb * bxy;
         const T axb = -Ptxxb * pf, ayb = Ptyyb * pf, bb = Ptxyb * pf;
         uxb += axb * (T(4) * ux2 - T(2)) * ux + bb * uy * (T(3) * ux2 - uy2);
         uyb += ayb * (T(4) * uy2 - T(2)) * uy + bb * ux * (ux2 - T(3) * uy2);
         const T q = k.inv4th2 * pfb;
-        fob[1] -= q;
-        fob[3] -= q;
-        fob[2] += q;
-        fob[4] += q;
+        W[2][1] -= q;  // populations 1 and 3
+        W[0][1] -= q;
+        W[1][2] += q;  // populations 2 and 4
+        W[1][0] += q;
       }
 #pragma unroll
-      for (int i = 0; i < Q; ++i) fob[i] += T(cx(i)) * psxb + T(cy(i)) * psyb;
-    }
-    // fo_i = P_i t_i
-    T X1bm = T(0), X1b0 = T(0), X1bp = T(0), Y1bm = T(0), Y1b0 = T(0), Y1bp = T(0);
-    T Y2bm = T(0), Y2b0 = T(0), Y2bp = T(0), Cxbm = T(0), Cxb0 = T(0), Cxbp = T(0);
+      for (int a = 0; a < 3; ++a)
 #pragma unroll
-    for (int i = 0; i < Q; ++i) {
-      Pb[i] = fob[i] * t[i];
-      const T tb = fob[i] * P[i];
-      const T cxv = sel(cx(i), Cxm, Cx0, Cxp), y2v = sel(cy(i), Y2m, Y20, Y2p);
-      if (cx(i) < 0) { X1bm += tb; Cxbm += tb * y2v; } else if (cx(i) > 0) { X1bp += tb; Cxbp += tb * y2v; } else { X1b0 += tb; Cxb0 += tb * y2v; }
-      if (cy(i) < 0) { Y1bm -= tb; Y2bm += tb * cxv; } else if (cy(i) > 0) { Y1bp -= tb; Y2bp += tb * cxv; } else { Y1b0 -= tb; Y2b0 += tb * cxv; }
+        for (int b = 0; b < 3; ++b) W[a][b] += T(a - 1) * psxb + T(b - 1) * psyb;
     }
-    const T n1b = (X1bm * Sxm + X1b0 * Sx0 + X1bp * Sxp) + (Y1bm * Sym + Y1b0 * Sy0 + Y1bp * Syp);
-    const T n2b = Y2bm * Cym + Y2b0 * Cy0 + Y2bp * Cyp;
-    Cxbm += T(2) * Cxm * (X1bm * n1);
-    Cxb0 += T(2) * Cx0 * (X1b0 * n1);
-    Cxbp += T(2) * Cxp * (X1bp * n1);
-    const T Cybm = Y2bm * n2 + T(2) * Cym * (Y1bm * n1);
-    const T Cyb0 = Y2b0 * n2 + T(2) * Cy0 * (Y1b0 * n1);
-    const T Cybp = Y2bp * n2 + T(2) * Cyp * (Y1bp * n1);
-    uxb -= (Cxbm + Cxb0) + Cxbp;
-    uyb -= (Cybm + Cyb0) + Cybp;
-    Nxxb = n1b * k.inv2th2;
-    Nxyb = n2b * (T(2) * k.inv2th2);
-  }
-  // feqs_i = rho P_i - w_i rho0, P_i = Phi_x Phi_y
+    // f^OReg_ab = [(A2_a B0_b - A0_a B2_b) N_xx + 2 A1_a B1_b N_xy] / (2 theta^2).
+    const T Cx[3] = {T(-1) - ux, -ux, T(1) - ux};
+    const T Cy[3] = {T(-1) - uy, -uy, T(1) - uy};
 #pragma unroll
-  for (int i = 0; i < Q; ++i) {
-    const T hx = sel(cx(i), hxm, hx0, hxp), hy = sel(cy(i), hym, hy0, hyp);
-    const T P = hx * hy;
-    rhob += feqsb[i] * P;
-    const T pb = (MODEL == M_BGK ? T(0) : Pb[i]) + feqsb[i] * rho;
-    const T bx = pb * hy, by = pb * hx;
-    if (cx(i) < 0) hxbm += bx; else if (cx(i) > 0) hxbp += bx; else hxb0 += bx;
-    if (cy(i) < 0) hybm += by; else if (cy(i) > 0) hybp += by; else hyb0 += by;
+    for (int c = 0; c < 3; ++c) {
+      A1[c] = A0[c] * Cx[c];
+      A2[c] = A1[c] * Cx[c];
+      const T tx = dA0[c] * Cx[c];
+      dA1[c] = tx - A0[c];
+      dA2[c] = tx * Cx[c] - T(2) * A1[c];
+      B1[c] = B0[c] * Cy[c];
+      B2[c] = B1[c] * Cy[c];
+      const T ty = dB0[c] * Cy[c];
+      dB1[c] = ty - B0[c];
+      dB2[c] = ty * Cy[c] - T(2) * B1[c];
+    }
+    T WB0[3], WB1[3], WB2[3], WdB0[3], WdB1[3], WdB2[3];
+    matvec(W, B0, WB0);
+    matvec(W, B1, WB1);
+    matvec(W, B2, WB2);
+    matvec(W, dB0, WdB0);
+    matvec(W, dB1, WdB1);
+    matvec(W, dB2, WdB2);
+    const T kx = Nxx * k.inv2th2, ky = Nxy * (T(2) * k.inv2th2);
+    Nxxb = k.inv2th2 * (dot(A2, WB0) - dot(A0, WB2));
+    Nxyb = (T(2) * k.inv2th2) * dot(A1, WB1);
+    uxb += kx * (dot(dA2, WB0) - dot(dA0, WB2)) + ky * dot(dA1, WB1);
+    uyb += kx * (dot(A2, WdB0) - dot(A0, WdB2)) + ky * dot(A1, WdB1);
   }
-  uxb += hxb0 * (T(-2) * ux) + hxbp * (ux + T(0.5)) + hxbm * (ux - T(0.5));
-  uyb += hyb0 * (T(-2) * uy) + hybp * (uy + T(0.5)) + hybm * (uy - T(0.5));
+  // Equilibrium part rho A0_a B0_b (shifted by a constant).
+  T FB0[3], FdB0[3];
+  matvec(F, B0, FB0);
+  matvec(F, dB0, FdB0);
+  T rhob = eq_scale * dot(A0, FB0);
+  uxb += eq_scale * rho * dot(dA0, FB0);
+  uyb += eq_scale * rho * dot(A0, FdB0);
   // Chain (rho, u, N) -> (rho, j, D, Pxy).
   const T Db = T(0.5) * Nxxb;
   const T Pxyb = Nxyb;
@@ -346,7 +344,7 @@ __device__ __forceinline__ void collide_vjp(const T fbs[Q], const T rec[NREC], c
   rhob -= (uxb * ux + uyb * uy) * rinv;
 #pragma unroll
   for (int i = 0; i < Q; ++i)
-    fbar[i] = direct[i] + rhob + T(cx(i)) * jxb + T(cy(i)) * jyb + T(cx(i) * cx(i) - cy(i) * cy(i)) * Db +
+    fbar[i] = direct_scale * fbs[i] + rhob + T(cx(i)) * jxb + T(cy(i)) * jyb + T(cx(i) * cx(i) - cy(i) * cy(i)) * Db +
               T(cx(i) * cy(i)) * Pxyb;
 }
 
