@@ -27,6 +27,18 @@ def sample_nodes(nx, ny, n, seed):
     return sorted(pts)
 
 
+def seam_nodes(nx, ny):
+    """Nodes on both sides of the places where the kernels' work is split: with lane-strided
+    rows (S = ceil(nx/64) groups, node x in group x mod S of lane x div S) the seam between
+    the two-step kernel's block columns of 8 groups (x mod S = 7 | 8), the wrap of the rotated
+    lanes at the end of a row (x = S - 1 | S), and row-block boundaries at multiples of 64
+    rows (y = 63 | 64), plus the last row."""
+    S = (nx + 63) // 64
+    xs = sorted({x for x in (7, 8, S - 1, S, 5 * S + 7, 5 * S + 8, nx - 1) if 0 <= x < nx})
+    ys = sorted({y for y in (0, 63, 64, ny // 2 - 1, ny // 2, ny - 1) if 0 <= y < ny})
+    return [(x, y) for x in xs for y in ys]
+
+
 def oracle_light_cone(fields, theta, nu, model, k, nodes):
     """Oracle populations at each sampled node after k steps, computed on a periodic patch of
     (2k+3)^2 nodes centred on it: after k steps the centre depends only on nodes within

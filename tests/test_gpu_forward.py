@@ -8,7 +8,7 @@ import pytest
 
 import lbm_inputs as inp
 import oracle
-from tests.gpu_util import gather_nodes, gpu_sim, oracle_light_cone, sample_nodes
+from tests.gpu_util import gather_nodes, gpu_sim, oracle_light_cone, sample_nodes, seam_nodes
 from tests.lbm_diag import eps_f
 
 pytestmark = pytest.mark.gpu
@@ -145,13 +145,15 @@ FULL = [
 def test_full_size_sampled_nodes(name, model, storage, pattern):
     """At the workloads' full sizes, in the launch configuration the benchmark times: the
     populations of sampled nodes after k steps against the oracle run on each node's
-    light cone (a periodic patch of (2k+3)^2 nodes)."""
+    light cone (a periodic patch of (2k+3)^2 nodes). The sample holds corners, random nodes
+    and both sides of every seam where the kernels split the work (block columns, the
+    rotated-lane wrap, row blocks)."""
     w = inp.WORKLOADS[name]
     fields = w.fields(seed=0)
     k = 9 if pattern == "aa" else 8
     sim = gpu_sim(w.nx, w.ny, w.theta, w.nu, model, storage, pattern, fields=fields)
     sim.step(k)
-    nodes = sample_nodes(w.nx, w.ny, 24, seed=1)
+    nodes = sorted(set(sample_nodes(w.nx, w.ny, 24, seed=1)) | set(seam_nodes(w.nx, w.ny)))
     got = gather_nodes(sim.populations(), nodes)
     ref = oracle_light_cone(fields, w.theta, w.nu, model, k, nodes)
     scale = max(np.max(np.abs(v)) for v in ref.values())
