@@ -283,6 +283,24 @@ def test_two_step_kernel_uneven_row_blocks(storage, nx, ny):
 
 
 
+@pytest.mark.parametrize("storage", ["f64", "f32"])
+@pytest.mark.parametrize("nx,ny", [(40960, 1), (20480, 2), (8192, 5)])
+def test_two_step_kernel_on_short_columns(storage, nx, ny):
+    """Columns of 1, 2 and 5 rows with the two-step kernel forced (two_step = 1): a block's
+    halo rows wrap onto its own rows (with ny = 1 phase A computes the only row three times).
+    7 steps bit for bit against single steps, and against the oracle."""
+    f0 = inp.random_populations(nx, ny, seed=17, amp=0.05)
+    a = gpu_sim(nx, ny, 0.4, 0.02, "complete", storage, "ab", f0=f0, two_step=1)
+    b = gpu_sim(nx, ny, 0.4, 0.02, "complete", storage, "ab", f0=f0, two_step=-1)
+    assert a.steps_per_launch == 2 and b.steps_per_launch == 1
+    a.step(7)
+    b.step(7)
+    fa = a.populations().cpu().numpy()
+    assert np.array_equal(fa, b.populations().cpu().numpy())
+    ref = oracle.run(f0, 0.4, 0.02, "complete", 7)
+    assert eps_f(fa, ref) <= {"f64": 1e-13, "f32": 1e-6}[storage]
+
+
 def test_steps_per_launch_follows_the_eligibility_rule():
     """Two steps per launch only for A-B, FP32/FP64 (16-bit: LBGK only), nx % 512 == 0, more than 2^15 storage
     positions and two_step >= 0; with two_step = 0 (the default) also only where the grid
