@@ -362,12 +362,13 @@ hipError_t launch_step2_m(const RunDesc& d, const void* src, void* dst, void* re
 }
 
 // Storage types and models served by the two-step kernel. Measured on MI355X (GLUPS,
-// single-step / two-step): complete model FP32 89.7 / 141 (4096^2), FP64 42.0 / 76
-// (8192^2); at 16-bit storage, where the OReg models' single-step kernels are already
-// limited by vector arithmetic, the halo recomputation makes two steps slower (complete
-// model, 8192^2: FP16 167 / 146, BF16 173 / 168), while LBGK's short collision leaves them
-// bandwidth-bound and two steps pay (FP16 179 / 181, BF16 179 / 222).
+// single-step / two-step): complete model FP32 89.7 / 141 (4096^2), FP64 42.0 / 76,
+// BF16 177 / 186 (8192^2); FP16, whose conversions to and from the LDS ring cost more than
+// BF16's, only with LBGK (complete model 167 / 154; LBGK 179 / 188; BF16 LBGK 178 / 232).
 template <class S> struct FuseSteps {
+  static constexpr bool value(int) { return true; }
+};
+template <> struct FuseSteps<_Float16> {
   static constexpr bool value(int model) { return model == M_BGK; }
 };
 template <> struct FuseSteps<float> {
