@@ -82,6 +82,22 @@ def test_taylor_green_theta03_fp32(model, steps, pattern):
     assert e <= TOL["f32"]
 
 
+@pytest.mark.parametrize("model,steps", [("complete", 2000), ("bgk", 2000)])
+def test_taylor_green_theta03_fp32_two_step_kernel(model, steps):
+    """The same FP32 workload for its full 2000 steps on a 512 x 256 box, where the two-step
+    kernel takes every pair of steps (two_step = 1; blocks of 2 rows, so every row is a block
+    edge): against the oracle at the FP32 bar."""
+    nx, ny, th, nu = 512, 256, 0.3, 0.005
+    fields = inp.taylor_green(nx, ny, 0.1, th, noise=1e-3, seed=0)
+    sim = gpu_sim(nx, ny, th, nu, model, "f32", "ab", fields=fields, two_step=1)
+    assert sim.steps_per_launch == 2
+    sim.step(steps)
+    ref = oracle.run(oracle.init_equilibrium(*fields, th), th, nu, model, steps)
+    e = eps_f(sim.populations().cpu().numpy(), ref)
+    print(f"eps_f {model} two-step {steps} steps: {e:.3e}")
+    assert e <= TOL["f32"]
+
+
 @pytest.mark.parametrize("storage,model", [("f16", "complete"), ("f16", "bgk"), ("bf16", "complete"),
                                            ("f32", "complete"), ("f64", "partial")])
 @pytest.mark.parametrize("pattern", ["ab", "aa"])
