@@ -52,9 +52,19 @@ class Simulation:
 
     # -- lifecycle ------------------------------------------------------------------------------
     def close(self):
+        """Destroy the context and release the workspace (its memory returns to torch's
+        allocator, which orders reuse after the work already queued on this stream)."""
         if self._ctx is not None:
             capi.lbm_destroy(self._ctx)
             self._ctx = None
+        self.workspace = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+        return False
 
     def __del__(self):
         try:

@@ -220,6 +220,22 @@ def test_moments_of_populations():
         assert sim.time == 3
 
 
+def test_simulation_as_context_manager():
+    """`with Simulation(...)` closes the context on exit; a closed simulation's calls raise
+    (the C ABI rejects the NULL context) instead of touching freed memory."""
+    import torch
+    from paper_2602_21242_amd import Simulation
+    from paper_2602_21242_amd.capi import LBMError
+    z = torch.zeros(16, 64, dtype=torch.float64, device="cuda")
+    with Simulation(64, 16, 0.4, 0.02, z, z) as sim:
+        sim.step(3)
+        assert sim.time == 3
+    assert sim.workspace is None
+    with pytest.raises(LBMError):
+        sim.step(1)
+    assert sim.time == -1
+
+
 def test_degenerate_calls_on_a_live_context():
     """Zero steps is a no-op; a negative count and a NULL population buffer are invalid, a
     16-bit output type unsupported, all rejected before any work with the state untouched;
