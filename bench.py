@@ -383,19 +383,24 @@ def bench_precision(inp, checkpoints=(100, 1000, 5000)):
 def bench_viscosity(thetas=(0.25, 1.0 / 3.0, 0.4, 0.5), machs=tuple(i / 10 for i in range(11)),
                     models=("bgk", "uc", "partial", "complete"), n=200, nu=1e-3, amp=1e-3, skip=200, steps=1000):
     """Effective viscosity nu~/nu of the pi/4-rotated decaying shear wave (the paper's first
-    benchmark: nu = 1e-3, amplitude 1e-3, 1200 iterations; here a doubly periodic n x n box)
-    over theta, the Mach number U/sqrt(theta) of the advecting flow and the model; FP64
-    storage. null = the wave blew up or grew."""
+    benchmark: nu = 1e-3, amplitude 1e-3, 1200 iterations, mean flow Ma/sqrt(6) in each
+    component) over theta, Ma and the model, FP64 storage, in both geometries: the paper's
+    1 x n column (u_x the shear wave along y) and a doubly periodic n x n box with the wave
+    along (-1, 1). null = the wave blew up or grew."""
     from paper_2602_21242_amd.diagnostics import rotated_wave_viscosity
     t0 = time.perf_counter()
-    table = {}
-    for th in thetas:
-        log(f"[viscosity] theta {th:.4f}")
-        table[f"{th:.4f}"] = {m: [rotated_wave_viscosity(m, th, nu, ma, n=n, A=amp, skip=skip, steps=steps)
-                                  for ma in machs] for m in models}
-    return {"workload": f"rotated shear wave {n}x{n}, nu={nu}, A={amp}, decay over steps {skip}..{skip + steps}, "
-                        f"FP64 storage", "mach": list(machs), "nu_ratio": table,
-            "seconds": time.perf_counter() - t0}
+    out = {"workload": f"rotated shear wave, n={n}, nu={nu}, A={amp}, decay over steps {skip}..{skip + steps}, "
+                       f"mean flow Ma/sqrt(6) per component, FP64 storage", "mach": list(machs)}
+    for geometry in ("column", "diagonal"):
+        table = {}
+        for th in thetas:
+            log(f"[viscosity] {geometry} theta {th:.4f}")
+            table[f"{th:.4f}"] = {m: [rotated_wave_viscosity(m, th, nu, ma, n=n, A=amp, skip=skip, steps=steps,
+                                                             geometry=geometry)
+                                      for ma in machs] for m in models}
+        out[f"nu_ratio_{geometry}"] = table
+    out["seconds"] = time.perf_counter() - t0
+    return out
 
 
 def bench_shear_layer(grids=(128, 256, 512), thetas=(0.4, 0.6), models=("bgk", "uc", "partial", "complete"),

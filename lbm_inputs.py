@@ -74,6 +74,15 @@ def rotated_shear_wave(n, A, U=0.0, rho0=1.0):
     return rho, ux, uy
 
 
+def shear_wave_column(n, A, Uc=0.0, rho0=1.0):
+    """The rotated shear wave on a 1 x n column (nx = 1, ny = n, both periodic):
+    u_x = u_y = Uc + A sin(2 pi y/n), so u_x is a shear wave and u_y a longitudinal wave
+    along y, both advected by the mean flow (Uc, Uc). Fields have shape (n, 1)."""
+    y = np.arange(n, dtype=np.float64)[:, None]
+    ux = Uc + A * np.sin(2 * math.pi * y / n)
+    return rho0 + 0.0 * y, ux, ux.copy()
+
+
 def random_phase_turbulence(n, kmin, kmax, u_rms, seed=0, rho0=1.0):
     """Solenoidal random-phase velocity field with an E(K) ~ K^(-5/3) shell spectrum.
 

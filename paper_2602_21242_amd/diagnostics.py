@@ -2,10 +2,11 @@
 
 * the Fourier amplitude of a velocity mode and the effective viscosity from its decay,
   with the rotated shear-wave measurement of the paper's first benchmark (Sec. 5, the
-  pi/4-rotated decaying shear wave), read on a doubly periodic n x n box:
-  u_x = u_y = U/sqrt(2) + A sin(2 pi (-x + y)/n), wave vector k = (2 pi/n)(-1, 1),
-  perturbation along (1, 1), so the mean flow U (along (1, 1)) advects the wave parallel
-  to its crests;
+  pi/4-rotated decaying shear wave, mean flow Ma/sqrt(6) in each component), in two
+  geometries: "diagonal", a doubly periodic n x n box with
+  u_x = u_y = Ma/sqrt(6) + A sin(2 pi (-x + y)/n) (wave vector along (-1, 1), perturbation
+  and mean flow along (1, 1)), and "column", the paper's 1 x n grid, where the wave can only
+  vary along y: u_x = u_y = Ma/sqrt(6) + A sin(2 pi y/n), u_x being the shear wave;
 * the isothermal shocktube of the paper's second benchmark (Sec. 5) between two bounce-back
   walls, against the exact solution of the isothermal Riemann problem;
 * vorticity, the vorticity thickness of the x-averaged profile and a count of vortex cores
@@ -40,38 +41,53 @@ def decay_viscosity(a0, a1, k2, steps):
     return -math.log(abs(a1) / abs(a0)) / (k2 * steps)
 
 
-def rotated_wave_fields(n, A, U, rho0=1.0, device=None):
-    """FP64 device fields (rho, u_x, u_y) of the rotated shear wave on an n x n box."""
+def rotated_wave_fields(n, A, Uc, rho0=1.0, device=None, geometry="diagonal"):
+    """FP64 device fields (rho, u_x, u_y) of the rotated shear wave with mean flow Uc in each
+    component: an n x n box ("diagonal") or an n x 1 column ("column")."""
     dev = torch.device(device) if device is not None else torch.device("cuda", torch.cuda.current_device())
-    x = torch.arange(n, device=dev, dtype=torch.float64)[None, :]
     y = torch.arange(n, device=dev, dtype=torch.float64)[:, None]
-    ux = U / math.sqrt(2.0) + A * torch.sin(2.0 * math.pi * (-x + y) / n)
+    if geometry == "column":
+        ux = Uc + A * torch.sin(2.0 * math.pi * y / n)
+        return torch.full((n, 1), rho0, device=dev, dtype=torch.float64), ux, ux.clone()
+    if geometry != "diagonal":
+        raise ValueError(f"unknown geometry {geometry!r}")
+    x = torch.arange(n, device=dev, dtype=torch.float64)[None, :]
+    ux = Uc + A * torch.sin(2.0 * math.pi * (-x + y) / n)
     return torch.full((n, n), rho0, device=dev, dtype=torch.float64), ux, ux.clone()
 
 
 def rotated_wave_viscosity(model, theta, nu, mach, n=200, A=1e-3, skip=200, steps=1000, storage="f64",
-                           pattern="ab"):
-    """nu~/nu of the rotated shear wave advected at U = mach sqrt(theta) (the lattice sound
-    speed is sqrt(theta)): the decay of the (-1, 1) mode between step `skip` and step
-    `skip + steps`, which leaves out the initial transient of the non-equilibrium modes.
-    Returns None when the run is unstable: not finite, the mode grows, or the velocity
-    deviates from the mean flow by more than 1.5 A anywhere (energy has gone into other
-    modes, so the decay of this one no longer measures a viscosity)."""
-    rho, ux, uy = rotated_wave_fields(n, A, mach * math.sqrt(theta))
-    sim = Simulation(n, n, theta, nu, ux, uy, rho=rho, model=model, storage=storage, pattern=pattern)
+                           pattern="ab", geometry="diagonal"):
+    """nu~/nu of the rotated shear wave advected by the mean flow Ma/sqrt(6) in each
+    component (the paper's initial condition): the decay between step `skip` and step
+    `skip + steps` (which leaves out the initial transient of the non-equilibrium modes) of
+    the (-1, 1) mode of u_x + u_y on the n x n box ("diagonal"), or of the first mode of
+    u_x along the 1 x n column ("column"). Returns None when the run is unstable: not finite,
+    the mode grows, or the velocity deviates from the mean flow by more than 1.5 A anywhere
+    (energy has gone into other modes, so the decay of this one no longer measures a
+    viscosity)."""
+    rho, ux, uy = rotated_wave_fields(n, A, mach / math.sqrt(6.0), geometry=geometry)
+    ny, nx = ux.shape
+    sim = Simulation(nx, ny, theta, nu, ux, uy, rho=rho, model=model, storage=storage, pattern=pattern)
+    if geometry == "column":
+        amp = lambda u, v: mode_amplitude(u, 0.0 * u, 0, 1)
+        k2 = (2.0 * math.pi / n) ** 2
+    else:
+        amp = lambda u, v: mode_amplitude(u, v, -1, 1)
+        k2 = 2.0 * (2.0 * math.pi / n) ** 2
     sim.step(skip)
     _, u0, v0 = sim.moments()
-    a0 = mode_amplitude(u0, v0, -1, 1)
+    a0 = amp(u0, v0)
     sim.step(steps)
     _, u1, v1 = sim.moments()
-    a1 = mode_amplitude(u1, v1, -1, 1)
+    a1 = amp(u1, v1)
     dev = max(float((u1 - u1.mean()).abs().max()), float((v1 - v1.mean()).abs().max()))
     sim.close()
     if not (math.isfinite(abs(a0)) and math.isfinite(abs(a1)) and math.isfinite(dev)):
         return None
     if abs(a1) == 0 or abs(a1) > abs(a0) or dev > 1.5 * A:
         return None
-    return decay_viscosity(a0, a1, 2.0 * (2.0 * math.pi / n) ** 2, steps) / nu
+    return decay_viscosity(a0, a1, k2, steps) / nu
 
 
 def isothermal_riemann(x, t, x0, rho_l, rho_r, c):
