@@ -90,3 +90,19 @@ def test_package_riemann_solution_matches_test_side(c):
     assert abs(rm1 - rm0) <= 1e-14 and abs(um1 - um0) <= 1e-14 and abs(s1 - s0) <= 1e-14
     np.testing.assert_allclose(r1.numpy(), r0, rtol=1e-14, atol=0)
     np.testing.assert_allclose(u1.numpy(), u0, rtol=0, atol=1e-15)
+
+
+@pytest.mark.parametrize("geometry", ["column", "diagonal"])
+def test_rotated_wave_fields_match_inputs(geometry):
+    """The package's rotated-wave initial fields (torch, on the CPU here) equal the test-side
+    generators: mean flow Uc in each component plus the sine along y (column, shape
+    (n, 1)) or along -x + y (n x n box)."""
+    import lbm_inputs as inp
+    n, A, Uc = 40, 1e-3, 0.3 / math.sqrt(6.0)
+    rho, ux, uy = d.rotated_wave_fields(n, A, Uc, device="cpu", geometry=geometry)
+    ref = inp.shear_wave_column(n, A, Uc=Uc) if geometry == "column" else inp.rotated_shear_wave(n, A, U=Uc * math.sqrt(2))
+    for a, b in zip((rho, ux, uy), ref):
+        assert tuple(a.shape) == b.shape
+        np.testing.assert_allclose(a.numpy(), b, rtol=0, atol=1e-15)
+    with pytest.raises(ValueError):
+        d.rotated_wave_fields(n, A, Uc, device="cpu", geometry="spiral")
