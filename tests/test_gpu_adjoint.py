@@ -80,6 +80,30 @@ def test_population_adjoint_with_two_step_launches(model, storage):
             assert err <= (1e-12 if storage == "f64" else 1e-5), (stride, err)
 
 
+@pytest.mark.parametrize("storage", ["f64", "f32"])
+def test_population_adjoint_small_grid_with_two_step_sweep(storage):
+    """512 x 64 (2^15 storage positions, so lbm_step replays step graphs of single steps and
+    steps_per_launch reports 1) with two_step = 1: the recorded forward run takes single
+    steps while the reverse sweep's recomputation and adjoint take pairs. N = 9, spacing 4:
+    against two_step = -1 to rounding and against the oracle's complex-step adjoint."""
+    import torch
+    nx, ny, th, nu, N = 512, 64, 0.4, 0.02, 9
+    f0 = inp.random_populations(nx, ny, seed=29, amp=0.05)
+    w = inp.random_direction((9, ny, nx), seed=30)
+    ref = _oracle_population_adjoint(f0, w, th, nu, "complete", N)
+    dtype = torch.float64 if storage == "f64" else torch.float32
+    got = {}
+    for ts in (1, -1):
+        sim = gpu_sim(nx, ny, th, nu, "complete", storage, "ab", f0=f0, record_steps=N, ckpt_stride=4, two_step=ts)
+        assert sim.steps_per_launch == 1
+        sim.step(N)
+        got[ts] = sim.adjoint_populations(_t(w, dtype)).cpu().numpy()
+    scale = np.max(np.abs(got[-1]))
+    assert np.max(np.abs(got[1] - got[-1])) <= (1e-14 if storage == "f64" else 1e-6) * scale
+    err = np.max(np.abs(got[1] - ref)) / np.max(np.abs(ref))
+    assert err <= (1e-12 if storage == "f64" else 1e-5), err
+
+
 @pytest.mark.parametrize("model", MODELS)
 def test_velocity_gradient_fp64_matches_oracle(model):
     """Gradient of the final kinetic energy E = 1/2 sum rho |u|^2 with respect to the initial
