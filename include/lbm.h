@@ -155,8 +155,7 @@ int64_t lbm_time(const lbm_ctx* ctx);
 
 /* Time steps one kernel launch of lbm_step advances for this context: 2 where the two-step
  * LDS-staged kernel applies, else 1 (-1 for a NULL context). It applies to the A-B pattern
- * with FP32, FP64 or BF16 storage (FP16 storage: LBGK only, the only model for which it
- * pays there), no walls, nx a multiple of 512, more than 2^15 storage
+ * (every storage type and model), no walls, nx a multiple of 512, more than 2^15 storage
  * positions and two_step >= 0; with two_step = 0 also only where the grid gives at least
  * three quarters of the device's compute units a block of 2 or more rows x 512 columns
  * (roughly (nx/512) floor(ny/2) >= 3 CUs/4), below which the single-step kernel is faster.

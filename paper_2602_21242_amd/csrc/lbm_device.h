@@ -42,19 +42,31 @@ template <class S> struct StorageTraits;
 template <> struct StorageTraits<double> {
   using T = double;
   static constexpr bool kShortCollide = false;
+  using Raw = double;
   static __device__ __forceinline__ double load(double v) { return v; }
+  static __device__ __forceinline__ double load_raw(double v) { return v; }
   static __device__ __forceinline__ double store(double v) { return v; }
 };
 template <> struct StorageTraits<float> {
   using T = float;
   static constexpr bool kShortCollide = false;
+  using Raw = float;
   static __device__ __forceinline__ float load(float v) { return v; }
+  static __device__ __forceinline__ float load_raw(float v) { return v; }
   static __device__ __forceinline__ float store(float v) { return v; }
 };
 template <> struct StorageTraits<_Float16> {
   using T = float;
   static constexpr bool kShortCollide = true;
+  // Loaded populations wait for their use as zero-extended 32-bit bit patterns. Kept as
+  // _Float16 values, the compiler packs pairs of them into one register right after the
+  // loads, which stalls on the loads there instead of at their first use (the two-step
+  // kernel's loads of the next row then no longer overlap the barrier and phase B).
+  using Raw = uint32_t;
   static __device__ __forceinline__ float load(_Float16 v) { return float(v); }
+  static __device__ __forceinline__ float load_raw(uint32_t r) {
+    return float(__builtin_bit_cast(_Float16, uint16_t(r)));
+  }
   static __device__ __forceinline__ _Float16 store(float v) { return _Float16(v); }
 };
 // bfloat16 as its raw 16 bits; stores convert with the hardware FP32 -> BF16 conversion
@@ -63,7 +75,9 @@ struct bf16_t { uint16_t bits; };
 template <> struct StorageTraits<bf16_t> {
   using T = float;
   static constexpr bool kShortCollide = true;
+  using Raw = bf16_t;
   static __device__ __forceinline__ float load(bf16_t v) { return __uint_as_float(uint32_t(v.bits) << 16); }
+  static __device__ __forceinline__ float load_raw(bf16_t v) { return load(v); }
   static __device__ __forceinline__ bf16_t store(float v) {
     const __bf16 h = static_cast<__bf16>(v);
     bf16_t r;

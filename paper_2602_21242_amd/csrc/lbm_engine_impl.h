@@ -361,23 +361,6 @@ hipError_t launch_step2_m(const RunDesc& d, const void* src, void* dst, void* re
   return hipGetLastError();
 }
 
-// Storage types and models served by the two-step kernel. Measured on MI355X (GLUPS,
-// single-step / two-step): complete model FP32 89.7 / 141 (4096^2), FP64 42.0 / 76,
-// BF16 177 / 186 (8192^2); FP16, whose conversions to and from the LDS ring cost more than
-// BF16's, only with LBGK (complete model 167 / 154; LBGK 179 / 188; BF16 LBGK 178 / 232).
-template <class S> struct FuseSteps {
-  static constexpr bool value(int) { return true; }
-};
-template <> struct FuseSteps<_Float16> {
-  static constexpr bool value(int model) { return model == M_BGK; }
-};
-template <> struct FuseSteps<float> {
-  static constexpr bool value(int) { return true; }
-};
-template <> struct FuseSteps<double> {
-  static constexpr bool value(int) { return true; }
-};
-
 // Row blocks of the two-step kernel. A block of h rows computes h + 2 rows of step 1 and h
 // of step 2, and a compute unit works through its share of the blocks in turn, so a launch
 // takes about ceil(blocks / CUs) (2 h + 2) row-steps of one block, h the tallest block.
@@ -412,7 +395,7 @@ inline int plan_row_blocks(const RunDesc& d, int mode) {
 
 template <class S>
 int Engine<S>::fuse_row_blocks(const RunDesc& d, int mode) {
-  return FuseSteps<S>::value(d.model) ? plan_row_blocks(d, mode) : 0;
+  return plan_row_blocks(d, mode);
 }
 
 template <class S>
@@ -422,17 +405,13 @@ int Engine<S>::adjoint_row_blocks(const RunDesc& d, int mode) {
 
 template <class S>
 hipError_t Engine<S>::step2(const RunDesc& d, const void* src, void* dst, void* rec1, void* rec2, hipStream_t st) {
-  if (d.fuse_rb < 1 || d.fuse_rb > d.ny || !FuseSteps<S>::value(d.model)) return hipErrorInvalidValue;
-  if (d.model == M_BGK) return launch_step2_m<S, M_BGK>(d, src, dst, rec1, rec2, st);
-  // The OReg models are instantiated only for the storage types that use them.
-  if constexpr (FuseSteps<S>::value(M_COMPLETE)) {
-    switch (d.model) {
-      case M_UC: return launch_step2_m<S, M_UC>(d, src, dst, rec1, rec2, st);
-      case M_PARTIAL: return launch_step2_m<S, M_PARTIAL>(d, src, dst, rec1, rec2, st);
-      default: return launch_step2_m<S, M_COMPLETE>(d, src, dst, rec1, rec2, st);
-    }
+  if (d.fuse_rb < 1 || d.fuse_rb > d.ny) return hipErrorInvalidValue;
+  switch (d.model) {
+    case M_BGK: return launch_step2_m<S, M_BGK>(d, src, dst, rec1, rec2, st);
+    case M_UC: return launch_step2_m<S, M_UC>(d, src, dst, rec1, rec2, st);
+    case M_PARTIAL: return launch_step2_m<S, M_PARTIAL>(d, src, dst, rec1, rec2, st);
+    default: return launch_step2_m<S, M_COMPLETE>(d, src, dst, rec1, rec2, st);
   }
-  return hipErrorInvalidValue;
 }
 
 template <class S>

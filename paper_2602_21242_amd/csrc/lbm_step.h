@@ -78,6 +78,19 @@ __device__ __forceinline__ void st1(S* p, S v) {
   __builtin_nontemporal_store(b, reinterpret_cast<B*>(p));
 }
 
+// A population load into the register form StorageTraits<S>::Raw (the storage type itself,
+// or for FP16 its 16 bits zero-extended to 32).
+template <class S>
+__device__ __forceinline__ typename StorageTraits<S>::Raw ld_raw(const S* p) {
+  using R = typename StorageTraits<S>::Raw;
+  if constexpr (std::is_same_v<R, S>) {
+    return ld1(p);
+  } else {
+    static_assert(sizeof(S) == 2 && std::is_same_v<R, uint32_t>, "raw registers: 16-bit storage only");
+    return R(__builtin_nontemporal_load(reinterpret_cast<const uint16_t*>(p)));
+  }
+}
+
 // Element at in-row position p of a population row: base (uniform: buffer + row +
 // population) plus the lane's 32-bit byte offset.
 template <class S>
@@ -151,7 +164,7 @@ k_step(const S* src, S* dst, Geo geo, Coef<typename StorageTraits<S>::T> k,
   char* dr[3] = {reinterpret_cast<char*>(dst) + ym * rsb, reinterpret_cast<char*>(dst) + y * rsb,
                  reinterpret_cast<char*>(dst) + yp * rsb};
 
-  S gs[NPT][Q];
+  typename Tr::Raw gs[NPT][Q];
 #pragma unroll
   for (int n = 0; n < NPT; ++n) {
     static_for<0, Q>([&](auto I) {
@@ -160,7 +173,7 @@ k_step(const S* src, S* dst, Geo geo, Coef<typename StorageTraits<S>::T> k,
       constexpr int slot = (PH == PH_AA_ODD) ? opp(i) : i;
       constexpr int dx = shift ? -cx(i) : 0;
       constexpr int dy = shift ? -cy(i) : 0;
-      gs[n][i] = ld1(at<S>(sr[dy + 1] + slot * psb, rp[n].template of<dx>()));
+      gs[n][i] = ld_raw<S>(at<S>(sr[dy + 1] + slot * psb, rp[n].template of<dx>()));
     });
   }
 
@@ -168,7 +181,7 @@ k_step(const S* src, S* dst, Geo geo, Coef<typename StorageTraits<S>::T> k,
   for (int n = 0; n < NPT; ++n) {
     T g[Q], out[Q], rv[NREC];
 #pragma unroll
-    for (int i = 0; i < Q; ++i) g[i] = Tr::load(gs[n][i]);
+    for (int i = 0; i < Q; ++i) g[i] = Tr::load_raw(gs[n][i]);
     collide<T, MODEL, Tr::kShortCollide>(g, out, k, REC ? rv : nullptr);
     if constexpr (REC) {
       char* rrow = reinterpret_cast<char*>(rec) + y * (size_t(rec_rs) * sizeof(T));
@@ -225,7 +238,8 @@ __device__ __forceinline__ void xcd_tile(int& bx, int& by) {
 }
 
 template <class S>
-__device__ __forceinline__ void load_pulled(const S* src, const Geo& geo, int r, const RowPos& rp, S gs[Q]) {
+__device__ __forceinline__ void load_pulled(const S* src, const Geo& geo, int r, const RowPos& rp,
+                                            typename StorageTraits<S>::Raw gs[Q]) {
   const int y = r < 0 ? r + geo.ny : (r >= geo.ny ? r - geo.ny : r);
   const int ym = (y == 0) ? geo.ny - 1 : y - 1;
   const int yp = (y == geo.ny - 1) ? 0 : y + 1;
@@ -234,7 +248,7 @@ __device__ __forceinline__ void load_pulled(const S* src, const Geo& geo, int r,
                        reinterpret_cast<const char*>(src) + yp * rsb};
   static_for<0, Q>([&](auto I) {
     constexpr int i = decltype(I)::value;
-    gs[i] = ld1(at<S>(sr[-cy(i) + 1] + i * psb, rp.template of<-cx(i)>()));
+    gs[i] = ld_raw<S>(at<S>(sr[-cy(i) + 1] + i * psb, rp.template of<-cx(i)>()));
   });
 }
 
@@ -270,14 +284,14 @@ k_step2(const S* __restrict__ src, S* __restrict__ dst, Geo geo, Coef<typename S
   const int pb = (s0 + w - 1) * kLanes + lane;  // phase-B output position
   const size_t rsb = size_t(geo.rs) * sizeof(S), psb = size_t(geo.ps) * sizeof(S);
 
-  S gs[Q];
+  typename Tr::Raw gs[Q];
   load_pulled<S>(src, geo, y0 - 1, ra, gs);
   for (int r = y0 - 1; r <= y1; ++r) {
     const int slot = (r - y0 + 1) % 3;
     {
       T g[Q], out[Q], rv[NREC];
 #pragma unroll
-      for (int i = 0; i < Q; ++i) g[i] = Tr::load(gs[i]);
+      for (int i = 0; i < Q; ++i) g[i] = Tr::load_raw(gs[i]);
       collide<T, MODEL, Tr::kShortCollide>(g, out, k, REC ? rv : nullptr);
 #pragma unroll
       for (int i = 0; i < Q; ++i) ring[slot][w][i][lane] = Tr::store(out[i]);

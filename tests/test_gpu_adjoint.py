@@ -70,7 +70,7 @@ def test_population_adjoint_with_two_step_launches(model, storage):
         for ts in (1, -1):
             sim = gpu_sim(nx, ny, th, nu, model, storage, "ab", f0=f0, record_steps=N, ckpt_stride=stride,
                           two_step=ts)
-            assert sim.steps_per_launch == (2 if ts == 1 and (storage != "f16" or model == "bgk") else 1)
+            assert sim.steps_per_launch == (2 if ts == 1 else 1)
             sim.step(N)
             got[ts] = sim.adjoint_populations(_t(w, dtype)).cpu().numpy()
         scale = np.max(np.abs(got[-1]))

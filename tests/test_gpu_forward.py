@@ -298,15 +298,15 @@ def test_step_graph_replays_match_single_launches(storage, pattern):
 @pytest.mark.parametrize("model", ["bgk", "uc", "partial", "complete"])
 def test_two_step_kernel_matches_single_steps(storage, model):
     """A-B runs of n >= 2 steps with FP32 or FP64 storage on grids with nx % 512 == 0 advance
-    two steps per launch through the LDS-staged kernel when asked to (two_step = 1; FP16
-    storage only with LBGK). 512 x 100 in blocks of 2 rows,
+    two steps per launch through the LDS-staged kernel when asked to (two_step = 1; every
+    storage type and model). 512 x 100 in blocks of 2 rows,
     7 steps (three fused launches and one single step) against a run advanced one
     lbm_step(1) call at a time: bit for bit; then against the oracle."""
     nx, ny, th, nu = 512, 100, 0.4, 0.02
     f0 = inp.random_populations(nx, ny, seed=41, amp=0.02)
     a = gpu_sim(nx, ny, th, nu, model, storage, "ab", f0=f0, two_step=1)
     b = gpu_sim(nx, ny, th, nu, model, storage, "ab", f0=f0, two_step=1)
-    assert a.steps_per_launch == (2 if storage != "f16" or model == "bgk" else 1)
+    assert a.steps_per_launch == 2
     a.step(7)
     for _ in range(7):
         b.step(1)
@@ -352,12 +352,12 @@ def test_two_step_kernel_on_short_columns(storage, nx, ny):
 
 
 def test_steps_per_launch_follows_the_eligibility_rule():
-    """Two steps per launch only for A-B, FP32/FP64/BF16 (FP16: LBGK only), nx % 512 == 0, more than 2^15 storage
+    """Two steps per launch only for A-B (any storage type and model), nx % 512 == 0, more than 2^15 storage
     positions and two_step >= 0; with two_step = 0 (the default) also only where the grid
     gives at least three quarters of the compute units (256 on MI355X) a block of >= 2 rows
     x 512 columns; every other context launches one step at a time."""
     cases = [((512, 100, "f32", "ab", 1), 2), ((512, 100, "f64", "ab", 1), 2), ((512, 100, "f32", "aa", 1), 1),
-             ((512, 100, "f16", "ab", 1), 1), ((500, 100, "f32", "ab", 1), 1), ((448, 100, "f32", "ab", 1), 1),
+             ((512, 100, "f16", "ab", 1), 2), ((500, 100, "f32", "ab", 1), 1), ((448, 100, "f32", "ab", 1), 1),
              ((512, 60, "f32", "ab", 1), 1), ((4096, 16, "f32", "ab", 1), 2),
              ((512, 100, "f32", "ab", 0), 1), ((4096, 16, "f32", "ab", 0), 1), ((512, 256, "f32", "ab", 0), 1),
              ((512, 512, "f32", "ab", 0), 2),
@@ -366,7 +366,7 @@ def test_steps_per_launch_follows_the_eligibility_rule():
     for (nx, ny, storage, pattern, two_step), expect in cases:
         sim = gpu_sim(nx, ny, 0.4, 0.02, "complete", storage, pattern, two_step=two_step)
         assert sim.steps_per_launch == expect, (nx, ny, storage, pattern, two_step)
-    for storage, model, expect in (("f16", "bgk", 2), ("bf16", "bgk", 2), ("bf16", "partial", 2), ("f16", "uc", 1),
-                                   ("f32", "uc", 2)):
+    for storage, model, expect in (("f16", "bgk", 2), ("bf16", "bgk", 2), ("bf16", "partial", 2), ("f16", "uc", 2),
+                                   ("f16", "partial", 2), ("f32", "uc", 2)):
         sim = gpu_sim(512, 100, 0.4, 0.02, model, storage, "ab", two_step=1)
         assert sim.steps_per_launch == expect, (storage, model)
