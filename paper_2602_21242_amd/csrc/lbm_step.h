@@ -252,6 +252,14 @@ __device__ __forceinline__ void load_pulled(const S* src, const Geo& geo, int r,
   });
 }
 
+// Storage types whose two-step kernel runs the rotated loop for its interior wavefronts
+// (see k_step2). Measured on MI355X, GLUPS, complete model unless noted, same machine,
+// interleaved: FP32 139.1 -> 140.8 (4096^2), 141.2 -> 142.3 (8192^2), LBGK 151.3 -> 154.4;
+// FP64 75.3 -> 74.4 and BF16 / FP16 182 -> 171 (8192^2; the 16-bit kernels need 70 instead
+// of 56 VGPRs with it, two blocks per compute unit instead of three), so only FP32 takes it.
+template <class S> struct RotatedFuseLoop : std::false_type {};
+template <> struct RotatedFuseLoop<float> : std::true_type {};
+
 // With REC the moments of both steps are recorded (rec1: first step, rec2: second step; the
 // layout and row stride rec_rs of k_step), by the interior wavefronts for the block's rows.
 template <class S, int MODEL, bool REC>
@@ -285,46 +293,90 @@ k_step2(const S* __restrict__ src, S* __restrict__ dst, Geo geo, Coef<typename S
   const size_t rsb = size_t(geo.rs) * sizeof(S), psb = size_t(geo.ps) * sizeof(S);
 
   typename Tr::Raw gs[Q];
-  load_pulled<S>(src, geo, y0 - 1, ra, gs);
-  for (int r = y0 - 1; r <= y1; ++r) {
+  // Phase A of row r: step 1 of the wavefront's node from gs into the ring slot of row r
+  // (plus its moments for the block's own rows).
+  auto phase_a = [&](const int r) {
     const int slot = (r - y0 + 1) % 3;
-    {
-      T g[Q], out[Q], rv[NREC];
+    T g[Q], out[Q], rv[NREC];
 #pragma unroll
-      for (int i = 0; i < Q; ++i) g[i] = Tr::load_raw(gs[i]);
-      collide<T, MODEL, Tr::kShortCollide>(g, out, k, REC ? rv : nullptr);
+    for (int i = 0; i < Q; ++i) g[i] = Tr::load_raw(gs[i]);
+    collide<T, MODEL, Tr::kShortCollide>(g, out, k, REC ? rv : nullptr);
 #pragma unroll
-      for (int i = 0; i < Q; ++i) ring[slot][w][i][lane] = Tr::store(out[i]);
-      if constexpr (REC) {
-        if (interior && r >= y0 && r < y1) {
-          char* rrow = reinterpret_cast<char*>(rec1) + r * (size_t(rec_rs) * sizeof(T));
-#pragma unroll
-          for (int j = 0; j < NREC; ++j) st1(at<T>(rrow + j * size_t(geo.ps) * sizeof(T), pb), rv[j]);
-        }
-      }
-    }
-    if (r < y1) load_pulled<S>(src, geo, r + 1, ra, gs);
-    __syncthreads();
-    if (interior && r > y0) {
-      const int yr = r - 1;
-      T g[Q], out[Q];
-      static_for<0, Q>([&](auto I) {
-        constexpr int i = decltype(I)::value;
-        g[i] = Tr::load(ring[(yr - cy(i) - y0 + 1) % 3][w - cx(i)][i][lane]);
-      });
-      T rv[NREC];
-      collide<T, MODEL, Tr::kShortCollide>(g, out, k, REC ? rv : nullptr);
-      if constexpr (REC) {
-        char* rrow = reinterpret_cast<char*>(rec2) + yr * (size_t(rec_rs) * sizeof(T));
+    for (int i = 0; i < Q; ++i) ring[slot][w][i][lane] = Tr::store(out[i]);
+    if constexpr (REC) {
+      if (interior && r >= y0 && r < y1) {
+        char* rrow = reinterpret_cast<char*>(rec1) + r * (size_t(rec_rs) * sizeof(T));
 #pragma unroll
         for (int j = 0; j < NREC; ++j) st1(at<T>(rrow + j * size_t(geo.ps) * sizeof(T), pb), rv[j]);
       }
-      char* drow = reinterpret_cast<char*>(dst) + yr * rsb;
+    }
+  };
+  // Phase B of row yr (interior wavefronts): step 2 from the ring rows yr - 1 .. yr + 1.
+  auto phase_b = [&](const int yr) {
+    T g[Q], out[Q];
+    static_for<0, Q>([&](auto I) {
+      constexpr int i = decltype(I)::value;
+      g[i] = Tr::load(ring[(yr - cy(i) - y0 + 1) % 3][w - cx(i)][i][lane]);
+    });
+    T rv[NREC];
+    collide<T, MODEL, Tr::kShortCollide>(g, out, k, REC ? rv : nullptr);
+    if constexpr (REC) {
+      char* rrow = reinterpret_cast<char*>(rec2) + yr * (size_t(rec_rs) * sizeof(T));
 #pragma unroll
-      for (int i = 0; i < Q; ++i) st1(at<S>(drow + i * psb, pb), Tr::store(out[i]));
+      for (int j = 0; j < NREC; ++j) st1(at<T>(rrow + j * size_t(geo.ps) * sizeof(T), pb), rv[j]);
+    }
+    char* drow = reinterpret_cast<char*>(dst) + yr * rsb;
+#pragma unroll
+    for (int i = 0; i < Q; ++i) st1(at<S>(drow + i * psb, pb), Tr::store(out[i]));
+  };
+  auto load = [&](const int r) { load_pulled<S>(src, geo, r, ra, gs); };
+
+  // Per row r = y0 - 1 .. y1 every wavefront runs phase A of r, issues the loads of r + 1,
+  // and passes two barriers; between them the interior wavefronts run phase B of r - 1
+  // (from r = y0 + 1 on). That is 2 (y1 - y0) + 4 barriers for every wavefront.
+  load(y0 - 1);
+  if (!RotatedFuseLoop<S>::value || !interior) {
+    for (int r = y0 - 1; r <= y1; ++r) {
+      phase_a(r);
+      if (r < y1) load(r + 1);
+      __syncthreads();
+      if (interior && r > y0) phase_b(r - 1);
+      __syncthreads();
+    }
+    return;
+  }
+  // Interior wavefronts, rotated: the same sequence, with the loop entered right after the
+  // loads of the next row. Vector-memory operations complete in issue order, and on every
+  // path into the loop those loads are the most recent ones; so phase A, which needs only
+  // them, waits with phase B's stores (issued after them) still in flight. (In the loop
+  // above, a path without stores -- halo wavefronts, the first rows -- joins one with them
+  // at phase A, and the wait there covers every store as well.)
+  phase_a(y0 - 1);
+  load(y0);
+  __syncthreads();
+  __syncthreads();
+  phase_a(y0);
+  load(y0 + 1);
+  __syncthreads();
+  __syncthreads();
+  phase_a(y0 + 1);
+  if (y0 + 1 < y1) {
+    load(y0 + 2);
+    for (int r = y0 + 2; r < y1; ++r) {
+      __syncthreads();
+      phase_b(r - 2);
+      __syncthreads();
+      phase_a(r);
+      load(r + 1);
     }
     __syncthreads();
+    phase_b(y1 - 2);
+    __syncthreads();
+    phase_a(y1);
   }
+  __syncthreads();
+  phase_b(y1 - 1);
+  __syncthreads();
 }
 
 // Two reverse steps per launch, staged through LDS like k_step2 (same blocks, halo
