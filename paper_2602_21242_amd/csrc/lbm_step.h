@@ -383,8 +383,10 @@ k_step2(const S* __restrict__ src, S* __restrict__ dst, Geo geo, Coef<typename S
 // wavefronts, XCD-aware tile order and three-row ring). Phase A computes fbar^n of every
 // wavefront's node at row r from fbar^{n+1} gathered at x + c_i and the records rec_hi of
 // step n; phase B computes fbar^{n-1} of row r - 1 for the interior wavefronts from the
-// ring and the records rec_lo of step n - 1, and stores it. The same operations in the same
-// order as two k_adjoint_step launches, so the result is bit-identical. fbar uses the
+// ring and the records rec_lo of step n - 1, and stores it. The same arithmetic as two
+// k_adjoint_step launches (equal up to the compiler's choice of fused multiply-adds, which
+// can differ between the two kernels: relative differences of order 1e-16 in FP64 and 1e-7
+// in FP32). fbar uses the
 // population layout in the compute type; requires nx % 64 == 0 and S % kFuseGroups == 0.
 template <class T>
 __device__ __forceinline__ void load_gathered(const T* src, const Geo& geo, int r, const RowPos& rp, T fs[Q]) {
@@ -434,37 +436,84 @@ k_adjoint_step2(const T* __restrict__ fbar_next, T* __restrict__ fbar, Geo geo, 
   const int pb = (s0 + w - 1) * kLanes + lane;
   const size_t rsb = size_t(geo.rs) * sizeof(T), psb = size_t(geo.ps) * sizeof(T);
 
-  T fs[Q], rv[NREC];
-  load_gathered<T>(fbar_next, geo, y0 - 1, ra, fs);
-  load_record<T>(rec_hi, geo, rec_rs, y0 - 1, ra.p0, rv);
-  for (int r = y0 - 1; r <= y1; ++r) {
+  T fs[Q], rv[NREC], rl[NREC];
+  // Phase A of row r: fbar^n of the wavefront's node (gathered fbar^{n+1} in fs, its
+  // records in rv) into the ring slot of row r.
+  auto phase_a = [&](const int r) {
     const int slot = (r - y0 + 1) % 3;
-    {
-      T fb[Q];
-      collide_vjp<T, MODEL>(fs, rv, k, fb);
+    T fb[Q];
+    collide_vjp<T, MODEL>(fs, rv, k, fb);
 #pragma unroll
-      for (int i = 0; i < Q; ++i) ring[slot][w][i][lane] = fb[i];
-    }
-    if (r < y1) {
-      load_gathered<T>(fbar_next, geo, r + 1, ra, fs);
-      load_record<T>(rec_hi, geo, rec_rs, r + 1, ra.p0, rv);
-    }
-    __syncthreads();
-    if (interior && r > y0) {
-      const int yr = r - 1;
-      T g[Q], fb[Q], rl[NREC];
-      load_record<T>(rec_lo, geo, rec_rs, yr, pb, rl);
-      static_for<0, Q>([&](auto I) {
-        constexpr int i = decltype(I)::value;
-        g[i] = ring[(yr + cy(i) - y0 + 1) % 3][w + cx(i)][i][lane];
-      });
-      collide_vjp<T, MODEL>(g, rl, k, fb);
-      char* orow = reinterpret_cast<char*>(fbar) + yr * rsb;
+    for (int i = 0; i < Q; ++i) ring[slot][w][i][lane] = fb[i];
+  };
+  // Phase B of row yr (interior wavefronts): fbar^{n-1} from the ring rows yr - 1 .. yr + 1
+  // and the records of step n - 1 in rl, stored.
+  auto phase_b = [&](const int yr) {
+    T g[Q], fb[Q];
+    static_for<0, Q>([&](auto I) {
+      constexpr int i = decltype(I)::value;
+      g[i] = ring[(yr + cy(i) - y0 + 1) % 3][w + cx(i)][i][lane];
+    });
+    collide_vjp<T, MODEL>(g, rl, k, fb);
+    char* orow = reinterpret_cast<char*>(fbar) + yr * rsb;
 #pragma unroll
-      for (int i = 0; i < Q; ++i) st1(at<T>(orow + i * psb, pb), fb[i]);
+    for (int i = 0; i < Q; ++i) st1(at<T>(orow + i * psb, pb), fb[i]);
+  };
+  auto load_a = [&](const int r) {
+    load_gathered<T>(fbar_next, geo, r, ra, fs);
+    load_record<T>(rec_hi, geo, rec_rs, r, ra.p0, rv);
+  };
+  auto load_b = [&](const int yr) { load_record<T>(rec_lo, geo, rec_rs, yr, pb, rl); };
+
+  // Per row r = y0 - 1 .. y1 every wavefront runs phase A of r, issues the loads of r + 1
+  // and passes two barriers; between them the interior wavefronts run phase B of r - 1
+  // (from r = y0 + 1 on) and then issue the records phase B of r will need (r < y1). The
+  // records are loaded one row ahead, after the stores: vector-memory operations complete
+  // in issue order, so records loaded after the next row's prefetch would make phase B
+  // wait for that prefetch as well.
+  load_a(y0 - 1);
+  if (!interior) {
+    for (int r = y0 - 1; r <= y1; ++r) {
+      phase_a(r);
+      if (r < y1) load_a(r + 1);
+      __syncthreads();
+      __syncthreads();
     }
-    __syncthreads();
+    return;
   }
+  // Interior wavefronts: the loop is entered right after the loads of the next row, the most
+  // recent operations on every path into it, so both waits in its body (phase B's records,
+  // issued before those loads, and phase A's loads, issued before phase B's stores and the
+  // next records) leave the later operations in flight.
+  phase_a(y0 - 1);
+  load_a(y0);
+  __syncthreads();
+  __syncthreads();
+  phase_a(y0);
+  load_a(y0 + 1);
+  __syncthreads();
+  load_b(y0);
+  __syncthreads();
+  phase_a(y0 + 1);
+  if (y0 + 1 < y1) {
+    load_a(y0 + 2);
+    for (int r = y0 + 2; r < y1; ++r) {
+      __syncthreads();
+      phase_b(r - 2);
+      load_b(r - 1);
+      __syncthreads();
+      phase_a(r);
+      load_a(r + 1);
+    }
+    __syncthreads();
+    phase_b(y1 - 2);
+    load_b(y1 - 1);
+    __syncthreads();
+    phase_a(y1);
+  }
+  __syncthreads();
+  phase_b(y1 - 1);
+  __syncthreads();
 }
 
 // One A-B time step with solid columns at x = 0 and x = nx - 1 (fullway bounce-back, the
