@@ -104,6 +104,33 @@ def test_population_adjoint_small_grid_with_two_step_sweep(storage):
     assert err <= (1e-12 if storage == "f64" else 1e-5), err
 
 
+@pytest.mark.parametrize("storage", ["f64", "f32"])
+@pytest.mark.parametrize("nx,ny", [(512, 1), (512, 5), (4096, 200)])
+def test_adjoint_pair_over_row_block_heights(storage, nx, ny):
+    """The two-step adjoint kernel's interior wavefronts run a prologue, a loop and an
+    epilogue whose lengths follow the row-block height h: 512 x 1 has h = 1, 512 x 5 blocks
+    of 2 and 3 rows, 4096 x 200 32 row blocks of 6 or 7 rows (the loop body runs). Sweep
+    with pairs (two_step = 1) against single adjoint steps (two_step = -1) to rounding, the
+    two small grids also against the oracle's complex-step adjoint. N = 9, spacing 4."""
+    import torch
+    th, nu, N = 0.4, 0.02, 9
+    f0 = inp.random_populations(nx, ny, seed=31, amp=0.05)
+    w = inp.random_direction((9, ny, nx), seed=32)
+    dtype = torch.float64 if storage == "f64" else torch.float32
+    got = {}
+    for ts in (1, -1):
+        sim = gpu_sim(nx, ny, th, nu, "complete", storage, "ab", f0=f0, record_steps=N, ckpt_stride=4, two_step=ts)
+        sim.step(N)
+        got[ts] = sim.adjoint_populations(_t(w, dtype)).cpu().numpy()
+        sim.close()
+    scale = np.max(np.abs(got[-1]))
+    assert np.max(np.abs(got[1] - got[-1])) <= (1e-14 if storage == "f64" else 1e-6) * scale
+    if nx * ny <= 4096:
+        ref = _oracle_population_adjoint(f0, w, th, nu, "complete", N)
+        err = np.max(np.abs(got[1] - ref)) / np.max(np.abs(ref))
+        assert err <= (1e-12 if storage == "f64" else 1e-5), err
+
+
 @pytest.mark.parametrize("model", MODELS)
 def test_velocity_gradient_fp64_matches_oracle(model):
     """Gradient of the final kinetic energy E = 1/2 sum rho |u|^2 with respect to the initial
