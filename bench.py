@@ -472,6 +472,21 @@ def bench_adjoint(inp):
         "steps": N, "ms_total": ms_sweep, "GLUPS_gradient_sweep": nodes * N / (ms_sweep * 1e-3) / 1e9,
         "note": "reverse sweep = recorded recomputation from each checkpoint + adjoint step per step"}
     del sim
+    # The same sweep with one checkpoint segment: the forward run kept the moments of every
+    # step (64 x 20 B per node), so the sweep is the adjoint kernels alone.
+    sim = make_sim(w, "complete", "f32", "ab", fields, record_steps=N, ckpt_stride=N)
+    sim.step(N)
+    sim.adjoint(None, z + 1e-3, z)  # warm-up
+    torch.cuda.synchronize()
+    s.record(sim.stream)
+    sim.adjoint(None, z + 1e-3, z)
+    e.record(sim.stream)
+    torch.cuda.synchronize()
+    ms_one = s.elapsed_time(e)
+    res["adjoint/tg4096/complete/f32/sweep_one_segment"] = {
+        "steps": N, "ms_total": ms_one, "GLUPS_gradient_sweep": nodes * N / (ms_one * 1e-3) / 1e9,
+        "note": "ckpt_stride = N: moments of every step kept from the forward run, no recomputation"}
+    del sim
     # End-to-end gradient of the final kinetic energy on the 1024^2 shear wave.
     from paper_2602_21242_amd import LBMFunction
     wa = inp.WORKLOADS["shear1024"]
@@ -492,6 +507,20 @@ def bench_adjoint(inp):
     res["gradient/shear1024/complete/f32/ab"] = {
         "steps": wa.steps, "s_total": dt, "GLUPS_end_to_end": wa.nx * wa.ny * wa.steps / dt / 1e9,
         "note": "forward with checkpoints + recomputation + adjoint, cache-resident size"}
+    cfg1 = dict(cfg, ckpt_stride=wa.steps)
+    for rep in range(2):
+        ux0 = t(ux).requires_grad_(True)
+        uy0 = t(uy).requires_grad_(True)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        r, vx, vy = LBMFunction.apply(ux0, uy0, cfg1)
+        E = 0.5 * (r * (vx * vx + vy * vy)).sum()
+        E.backward()
+        torch.cuda.synchronize()
+        dt1 = time.perf_counter() - t0
+    res["gradient/shear1024/complete/f32/ab/one_segment"] = {
+        "steps": wa.steps, "s_total": dt1, "GLUPS_end_to_end": wa.nx * wa.ny * wa.steps / dt1 / 1e9,
+        "note": "ckpt_stride = steps: forward keeps every step's moments (10.5 GB), sweep without recomputation"}
     return res
 
 

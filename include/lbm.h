@@ -75,7 +75,12 @@ typedef struct {
   int32_t model;         /* lbm_model */
   int32_t storage;       /* lbm_dtype of the stored populations */
   int32_t pattern;       /* lbm_pattern */
-  int32_t ckpt_stride;   /* adjoint checkpoint spacing in steps; 0: ceil(sqrt(record_steps)) */
+  int32_t ckpt_stride;   /* adjoint checkpoint spacing s in steps (values above record_steps
+                            count as record_steps); 0: ceil(sqrt(record_steps)). The reverse
+                            sweep recomputes every segment but the last from its checkpoint,
+                            so s >= record_steps (one segment, the moments of every step kept:
+                            record_steps x 5 x sizeof(compute type) bytes per node) recomputes
+                            nothing */
   int64_t record_steps;  /* 0: no adjoint; N > 0: checkpoint the first N steps for lbm_adjoint */
   int32_t two_step;      /* two steps per launch (see lbm_steps_per_launch): 0 where the grid is
                             large enough for it to pay, 1 wherever the layout allows, -1 never */
@@ -112,8 +117,9 @@ lbm_status lbm_init(const lbm_params* p, void* d_workspace, size_t workspace_byt
 
 /* Advance n >= 0 time steps (eq:lbe: collide, then stream); n = 0 does nothing and n < 0
  * is LBM_ERR_INVALID_ARGUMENT. While the context records (record_steps > 0), the state at
- * every checkpoint time below record_steps is saved; stepping past record_steps is allowed
- * but disables lbm_adjoint. */
+ * every checkpoint time below record_steps is saved and the steps of the last checkpoint
+ * segment also write their moments for the reverse sweep; stepping past record_steps is
+ * allowed but disables lbm_adjoint. */
 lbm_status lbm_step(lbm_ctx* ctx, int64_t n);
 
 /* Density and velocity rho = sum_i f_i, u = sum_i c_i f_i / rho of the pre-collision
@@ -140,8 +146,10 @@ lbm_status lbm_invariants(lbm_ctx* ctx, double out[3]);
  * Given dJ/drho, dJ/du_x, dJ/du_y of the moments at t = N (compute-type [ny][nx]
  * arrays; d_rho_bar may be NULL for zero), writes dJ/du_x and dJ/du_y of the initial
  * velocity fields passed to lbm_init (rho held fixed) to d_ux0_bar, d_uy0_bar.
- * Uses sqrt(N)-step checkpoints with recomputation; the state at t = N is restored
- * before returning, so the call may be repeated. */
+ * Uses the checkpoints of the forward run (every ckpt_stride steps, sqrt(N) by default) and
+ * recomputes each segment but the last, whose moments the forward run kept; the state at
+ * t = N is restored before returning, so the call may be repeated (a repeated call also
+ * recomputes the last segment unless there is only one). */
 lbm_status lbm_adjoint(lbm_ctx* ctx, const void* d_rho_bar, const void* d_ux_bar,
                        const void* d_uy_bar, void* d_ux0_bar, void* d_uy0_bar);
 

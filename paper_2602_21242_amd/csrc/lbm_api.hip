@@ -97,7 +97,7 @@ Plan make_plan(const lbm_params& p) {
   if (p.record_steps > 0) {
     const int64_t N = p.record_steps;
     pl.stride = p.ckpt_stride > 0 ? p.ckpt_stride : int64_t(std::ceil(std::sqrt(double(N))));
-    if (pl.stride < 1) pl.stride = 1;
+    pl.stride = std::max<int64_t>(1, std::min<int64_t>(pl.stride, N));
     pl.nck = (N + pl.stride - 1) / pl.stride;
     pl.ckpt_off = off;
     off += size_t(pl.nck + 1) * pl.pop_bytes;
@@ -146,6 +146,9 @@ struct lbm_ctx {
   int64_t time = 0;
   int cur = 0;            // A-B: buffer holding the state
   bool rec_valid = false; // recorded run usable by the adjoint
+  // The record slots hold the moments of the last segment's steps, written by the forward
+  // run, so the reverse sweep need not recompute that segment.
+  bool last_seg_recorded = false;
   // Step graphs, built on first use: [A-B buffer index or AA phase parity at the start].
   hipStream_t capture = nullptr;  // private stream, used only to record the graphs
   hipGraphExec_t graph[2] = {nullptr, nullptr};
@@ -296,22 +299,29 @@ lbm_status restore(lbm_ctx* c, int64_t slot, int64_t t) {
 // holds dJ/df^0. Segment k (steps [k s, min((k+1) s, N))) is recomputed from its checkpoint
 // while recording moments (two steps per launch where the two-step kernel applies; the
 // first launch reads the checkpoint slot directly, so no copy restores it), then traversed
-// backwards with the adjoint kernel.
+// backwards with the adjoint kernel. The last segment's moments are usually still in the
+// slots from the forward run, which recorded them; with a single segment (stride >= N)
+// nothing is recomputed at all.
 lbm_status sweep(lbm_ctx* c, int* out_b) {
   const int64_t N = c->p.record_steps, s = c->plan.stride;
   int b = 0;
   for (int64_t k = c->plan.nck - 1; k >= 0; --k) {
     const int64_t t0 = k * s, t1 = std::min(t0 + s, N);
-    c->time = t0;
-    const bool fz = fused_ok(c);
-    lbm_status st = (fz && t1 - t0 >= 2) ? do_step2(c, c->ckpt(k), 0, c->rec_slot(0), c->rec_slot(1))
-                                         : step_from(c, c->ckpt(k), c->rec_slot(0));
-    if (st != LBM_OK) return st;
-    while (c->time < t1) {
-      const int64_t j = c->time - t0;
-      st = (fz && t1 - c->time >= 2) ? do_step2(c, c->state(), 1 - c->cur, c->rec_slot(j), c->rec_slot(j + 1))
-                                     : do_step(c, c->rec_slot(j));
+    lbm_status st = LBM_OK;
+    if (!(k == c->plan.nck - 1 && c->last_seg_recorded)) {
+      c->time = t0;
+      const bool fz = fused_ok(c);
+      st = (fz && t1 - t0 >= 2) ? do_step2(c, c->ckpt(k), 0, c->rec_slot(0), c->rec_slot(1))
+                                : step_from(c, c->ckpt(k), c->rec_slot(0));
       if (st != LBM_OK) return st;
+      while (c->time < t1) {
+        const int64_t j = c->time - t0;
+        st = (fz && t1 - c->time >= 2) ? do_step2(c, c->state(), 1 - c->cur, c->rec_slot(j), c->rec_slot(j + 1))
+                                       : do_step(c, c->rec_slot(j));
+        if (st != LBM_OK) return st;
+      }
+      // The slots now hold this segment's moments.
+      c->last_seg_recorded = false;
     }
     // Reverse steps t = t1 - 1 .. t0, two per launch (t and t - 1) where the two-step adjoint
     // kernel applies.
@@ -439,16 +449,23 @@ lbm_status lbm_step(lbm_ctx* c, int64_t n) {
     const int64_t N = c->p.record_steps;
     const bool small = is_small(c);
     const bool fused = !small && fused_ok(c);
+    const int64_t t_last = N > 0 ? (c->plan.nck - 1) * c->plan.stride : 0;  // last segment's start
     for (int64_t k = 0; k < n;) {
       const bool recording = N > 0 && c->rec_valid && c->time < N;
       if (recording && c->time % c->plan.stride == 0)
         HIP_TRY(hipMemcpyAsync(c->ckpt(c->time / c->plan.stride), c->state(), c->plan.pop_bytes,
                                hipMemcpyDeviceToDevice, c->stream));
-      // A pair of steps must not pass over a checkpoint time of the recorded window.
+      // Steps of the last segment keep their moments for the reverse sweep (slot t - t_last).
+      const bool keep = recording && c->time >= t_last;
+      // A pair of steps must not pass over a checkpoint time of the recorded window, nor
+      // over its end while keeping moments.
       const int64_t mid = c->time + 1;
-      if (fused && n - k >= 2 && !(recording && mid < N && mid % c->plan.stride == 0)) {
-        s = do_step2(c, c->state(), 1 - c->cur, nullptr, nullptr);
+      if (fused && n - k >= 2 && !(recording && mid < N && mid % c->plan.stride == 0) && !(keep && mid >= N)) {
+        const int64_t j = c->time - t_last;
+        s = keep ? do_step2(c, c->state(), 1 - c->cur, c->rec_slot(j), c->rec_slot(j + 1))
+                 : do_step2(c, c->state(), 1 - c->cur, nullptr, nullptr);
         if (s != LBM_OK) return s;
+        if (keep && c->time == N) c->last_seg_recorded = true;
         k += 2;
         continue;
       }
@@ -461,8 +478,9 @@ lbm_status lbm_step(lbm_ctx* c, int64_t n) {
         k += kGraphSteps;
         continue;
       }
-      s = do_step(c, nullptr);
+      s = do_step(c, keep ? c->rec_slot(c->time - t_last) : nullptr);
       if (s != LBM_OK) return s;
+      if (keep && c->time == N) c->last_seg_recorded = true;
       ++k;
     }
     return LBM_OK;
@@ -507,6 +525,7 @@ lbm_status lbm_set_populations(lbm_ctx* c, const double* d_f) {
     if (!d_f) return fail(LBM_ERR_INVALID_ARGUMENT, "input is NULL");
     DeviceGuard g(c->device);
     if (c->time != 0) c->rec_valid = false;
+    c->last_seg_recorded = false;
     return dispatch(c->p.storage, [&](auto eng) -> lbm_status {
       using E = decltype(eng);
       hipError_t e = E::set(c->d, c->layout(c->time), c->state(), d_f, c->stream);

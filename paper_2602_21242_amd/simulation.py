@@ -18,7 +18,9 @@ class Simulation:
 
     model: "bgk" | "uc" | "partial" | "complete"; storage: "f64" | "f32" | "bf16" | "f16";
     pattern: "ab" | "aa". record_steps > 0 checkpoints the first record_steps steps for
-    adjoint() (sqrt(N) checkpoints by default, or every ckpt_stride steps). two_step: 0 runs
+    adjoint() (sqrt(N) checkpoints by default, or every ckpt_stride steps; the forward run
+    keeps the last segment's moments, so ckpt_stride >= record_steps needs no recomputation
+    at record_steps x 5 x 4 (FP64: x 8) bytes per node). two_step: 0 runs
     two steps per launch where the grid is large enough for it to pay, 1 wherever the layout
     allows, -1 never (results are bit-identical). walls: solid bounce-back columns at x = 0
     and x = nx - 1 (A-B pattern, no recording).
@@ -138,7 +140,8 @@ class Simulation:
 
 class LBMFunction(torch.autograd.Function):
     """(u_x0, u_y0) -> (rho, u_x, u_y) after `steps` steps, differentiable through the
-    library's discrete adjoint (sqrt(N) checkpointing). The initial density is held fixed.
+    library's discrete adjoint (sqrt(N) checkpointing by default; ckpt_stride=steps keeps the
+    moments of every step instead and skips recomputation). The initial density is held fixed.
 
     Usage: rho, ux, uy = LBMFunction.apply(ux0, uy0, config) with
     config = dict(nx=..., ny=..., theta=..., nu=..., steps=..., model=..., storage=...,

@@ -104,6 +104,40 @@ def test_population_adjoint_small_grid_with_two_step_sweep(storage):
     assert err <= (1e-12 if storage == "f64" else 1e-5), err
 
 
+@pytest.mark.parametrize("pattern", ["ab", "aa"])
+@pytest.mark.parametrize("storage", ["f64", "f32"])
+def test_adjoint_uses_the_forward_runs_last_segment(storage, pattern):
+    """The forward run keeps the moments of its last checkpoint segment, and the reverse
+    sweep recomputes only the other segments; with a single segment (spacing >= N) it
+    recomputes nothing. 512 x 80 (two steps per launch for A-B), N = 11, spacing 4
+    (segments 4, 4, 3), 11 and 50 (one segment), the forward advanced in one call and in
+    calls of 3, 1, 2 and 5 steps (pairs and single steps meeting the last segment's start
+    and end), each adjoint taken twice (the second call recomputes the last segment when
+    there are several). Every result against the oracle's complex-step adjoint and against
+    the first one to rounding."""
+    import torch
+    nx, ny, th, nu, N = 512, 80, 0.4, 0.02, 11
+    f0 = inp.random_populations(nx, ny, seed=33, amp=0.05)
+    w = inp.random_direction((9, ny, nx), seed=34)
+    ref = _oracle_population_adjoint(f0, w, th, nu, "complete", N)
+    dtype = torch.float64 if storage == "f64" else torch.float32
+    results = []
+    for stride in (4, 11, 50):
+        for pieces in ((N,), (3, 1, 2, 5)):
+            sim = gpu_sim(nx, ny, th, nu, "complete", storage, pattern, f0=f0, record_steps=N, ckpt_stride=stride,
+                          two_step=1)
+            for n in pieces:
+                sim.step(n)
+            for _ in range(2):
+                results.append(sim.adjoint_populations(_t(w, dtype)).cpu().numpy())
+            sim.close()
+    scale = np.max(np.abs(ref))
+    for k, r in enumerate(results):
+        err = np.max(np.abs(r - ref)) / scale
+        assert err <= (1e-12 if storage == "f64" else 1e-5), (k, err)
+        assert np.max(np.abs(r - results[0])) <= (1e-14 if storage == "f64" else 1e-6) * scale, k
+
+
 @pytest.mark.parametrize("storage", ["f64", "f32"])
 @pytest.mark.parametrize("nx,ny", [(512, 1), (512, 5), (4096, 200)])
 def test_adjoint_pair_over_row_block_heights(storage, nx, ny):
