@@ -72,6 +72,13 @@ def test_workspace_plan(capi, storage, esize, tsize, pattern, nbuf):
     s, m2 = capi.lbm_workspace_bytes(_params(capi, nx=nx, ny=ny, storage=storage, pattern=pattern, record_steps=N,
                                              ckpt_stride=100))
     assert m2 == n + (5 + 1) * pop + 100 * rec + 2 * fbar
+    # One segment: a spacing of N or more keeps the moments of all N steps (N record slots,
+    # one checkpoint plus the slot of the final state), larger spacings count as N.
+    for big in (N, N + 1, 4 * N):
+        s, m3 = capi.lbm_workspace_bytes(_params(capi, nx=nx, ny=ny, storage=storage, pattern=pattern,
+                                                 record_steps=N, ckpt_stride=big))
+        assert s == capi.LBM_OK
+        assert m3 == n + (1 + 1) * pop + N * rec + 2 * fbar, big
 
 
 BAD = [dict(nx=0), dict(ny=0), dict(nx=-3), dict(theta=0.0), dict(theta=1.0), dict(theta=float("nan")),
