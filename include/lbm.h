@@ -26,8 +26,10 @@
  *    without waiting; lbm_invariants waits for the stream.
  *  - Errors: every call returns an lbm_status; no C++ exception crosses the ABI.
  *    lbm_last_error() returns a thread-local description of the last failure.
- *    Invalid arguments are rejected before any work is enqueued. Non-finite populations
- *    are not checked per step; lbm_invariants reports them.
+ *    Invalid arguments are rejected before any work is enqueued. After LBM_ERR_HIP from
+ *    lbm_step or lbm_adjoint* (work already enqueued) the context's state and time are
+ *    unspecified; lbm_destroy is still valid. Non-finite populations are not checked per
+ *    step; lbm_invariants reports them.
  *  - Compute type: FP64 when storage is LBM_F64, FP32 otherwise. Adjoint inputs and
  *    outputs use the compute type.
  */

@@ -309,6 +309,9 @@ lbm_status sweep(lbm_ctx* c, int* out_b) {
     const int64_t t0 = k * s, t1 = std::min(t0 + s, N);
     lbm_status st = LBM_OK;
     if (!(k == c->plan.nck - 1 && c->last_seg_recorded)) {
+      // The slots are about to hold this segment's moments (cleared first, so that a sweep
+      // that fails part-way never leaves the flag on overwritten slots).
+      c->last_seg_recorded = false;
       c->time = t0;
       const bool fz = fused_ok(c);
       st = (fz && t1 - t0 >= 2) ? do_step2(c, c->ckpt(k), 0, c->rec_slot(0), c->rec_slot(1))
@@ -320,8 +323,6 @@ lbm_status sweep(lbm_ctx* c, int* out_b) {
                                        : do_step(c, c->rec_slot(j));
         if (st != LBM_OK) return st;
       }
-      // The slots now hold this segment's moments.
-      c->last_seg_recorded = false;
     }
     // Reverse steps t = t1 - 1 .. t0, two per launch (t and t - 1) where the two-step adjoint
     // kernel applies.
