@@ -40,11 +40,18 @@ def _strip_comments(text):
     return "\n".join(line.rstrip() for line in text.splitlines() if line.strip())
 
 
+# Host-only source of the library (the C ABI's orchestration: no kernel, no launch geometry).
+HOST_ONLY_SOURCES = ("lbm_api.hip",)
+
+
 def kernel_source_hash():
-    """sha256 (first 16 hex digits) of the library sources under csrc/, comments and blank
-    lines removed, so that counters taken on the same code stay valid across comment edits."""
+    """sha256 (first 16 hex digits) of the library's device code and launch configuration
+    (every file under csrc/ but the host-only C ABI), comments and blank lines removed, so
+    that counters taken on the same kernels stay valid across comment and host-side edits."""
     h = hashlib.sha256()
     for p in sorted(glob.glob(os.path.join(ROOT, "paper_2602_21242_amd", "csrc", "*"))):
+        if os.path.basename(p) in HOST_ONLY_SOURCES:
+            continue
         with open(p, encoding="utf-8") as fh:
             h.update(os.path.basename(p).encode())
             h.update(_strip_comments(fh.read()).encode())
