@@ -159,7 +159,13 @@ struct lbm_ctx {
     if (capture) (void)hipStreamDestroy(capture);
   }
 
-  void* state() const { return ws + plan.pop_off[p.pattern == LBM_AB ? cur : 0]; }
+  // The state lives in population buffer cur (A-B) or 0 (AA) or, during a recorded run,
+  // in the checkpoint slot state_slot: a step that ends at a checkpoint time writes its
+  // output there instead of copying it afterwards, and the next step reads it from there.
+  int64_t state_slot = -1;
+  void* state() const {
+    return state_slot >= 0 ? ckpt(state_slot) : ws + plan.pop_off[p.pattern == LBM_AB ? cur : 0];
+  }
   lbm::LayoutSel layout(int64_t t) const {
     if (p.pattern == LBM_AB) return {1, 0};
     return (t & 1) ? lbm::LayoutSel{1, 1} : lbm::LayoutSel{0, 0};
@@ -202,8 +208,12 @@ lbm_status check_ctx(const lbm_ctx* c) {
   return LBM_OK;
 }
 
-// One time step of the current pattern; rec != nullptr also writes the moment record.
+lbm_status step_from(lbm_ctx* c, const void* src, void* rec);
+
+// One time step of the current pattern; rec != nullptr also writes the moment record. A
+// state held in a checkpoint slot is stepped out of place into population buffer 0.
 lbm_status do_step(lbm_ctx* c, void* rec) {
+  if (c->state_slot >= 0) return step_from(c, c->state(), rec);
   return dispatch(c->p.storage, [&](auto eng) -> lbm_status {
     using E = decltype(eng);
     hipError_t e;
@@ -229,7 +239,28 @@ lbm_status do_step2(lbm_ctx* c, const void* src, int dst, void* rec1, void* rec2
     const hipError_t e = E::step2(c->d, src, c->ws + c->plan.pop_off[dst], rec1, rec2, c->stream);
     if (e != hipSuccess) return fail(LBM_ERR_HIP, std::string("two-step kernel launch: ") + hipGetErrorString(e));
     c->cur = dst;
+    c->state_slot = -1;
     c->time += 2;
+    return LBM_OK;
+  });
+}
+
+// One step (npair = 1) or an A-B pair (npair = 2) from the current state into checkpoint
+// slot k, which then holds the state. Out of place, so valid for both AA phases as well.
+lbm_status step_into_ckpt(lbm_ctx* c, int npair, int64_t k) {
+  return dispatch(c->p.storage, [&](auto eng) -> lbm_status {
+    using E = decltype(eng);
+    hipError_t e;
+    if (npair == 2) {
+      e = E::step2(c->d, c->state(), c->ckpt(k), nullptr, nullptr, c->stream);
+    } else {
+      const int ph = c->p.pattern == LBM_AB ? lbm::PH_AB : ((c->time & 1) ? lbm::PH_AA_ODD : lbm::PH_AA_EVEN);
+      e = E::step(c->d, ph, c->state(), c->ckpt(k), nullptr, c->stream);
+    }
+    if (e != hipSuccess) return fail(LBM_ERR_HIP, std::string("step kernel launch: ") + hipGetErrorString(e));
+    c->state_slot = k;
+    c->cur = 0;
+    c->time += npair;
     return LBM_OK;
   });
 }
@@ -283,6 +314,7 @@ lbm_status step_from(lbm_ctx* c, const void* src, void* rec) {
     const hipError_t e = E::step(c->d, ph, src, c->ws + c->plan.pop_off[0], rec, c->stream);
     if (e != hipSuccess) return fail(LBM_ERR_HIP, std::string("step kernel launch: ") + hipGetErrorString(e));
     c->cur = 0;
+    c->state_slot = -1;
     ++c->time;
     return LBM_OK;
   });
@@ -291,6 +323,7 @@ lbm_status step_from(lbm_ctx* c, const void* src, void* rec) {
 lbm_status restore(lbm_ctx* c, int64_t slot, int64_t t) {
   HIP_TRY(hipMemcpyAsync(c->ws + c->plan.pop_off[0], c->ckpt(slot), c->plan.pop_bytes, hipMemcpyDeviceToDevice, c->stream));
   c->cur = 0;
+  c->state_slot = -1;
   c->time = t;
   return LBM_OK;
 }
@@ -426,6 +459,7 @@ lbm_status lbm_init(const lbm_params* p, void* d_workspace, size_t workspace_byt
     c->time = 0;
     c->cur = 0;
     c->rec_valid = p->record_steps > 0;
+    c->state_slot = c->rec_valid ? 0 : -1;  // a recorded run's initial state is checkpoint 0
     s = dispatch(p->storage, [&](auto eng) -> lbm_status {
       using E = decltype(eng);
       hipError_t e = E::init(c->d, c->layout(0), c->state(), d_rho, d_ux, d_uy, c->stream);
@@ -453,7 +487,9 @@ lbm_status lbm_step(lbm_ctx* c, int64_t n) {
     const int64_t t_last = N > 0 ? (c->plan.nck - 1) * c->plan.stride : 0;  // last segment's start
     for (int64_t k = 0; k < n;) {
       const bool recording = N > 0 && c->rec_valid && c->time < N;
-      if (recording && c->time % c->plan.stride == 0)
+      // The checkpoint of a checkpoint time: normally the step that ended here wrote the
+      // state into its slot; otherwise (a state replaced at t = 0) it is copied.
+      if (recording && c->time % c->plan.stride == 0 && c->state_slot != c->time / c->plan.stride)
         HIP_TRY(hipMemcpyAsync(c->ckpt(c->time / c->plan.stride), c->state(), c->plan.pop_bytes,
                                hipMemcpyDeviceToDevice, c->stream));
       // Steps of the last segment keep their moments for the reverse sweep (slot t - t_last).
@@ -461,7 +497,19 @@ lbm_status lbm_step(lbm_ctx* c, int64_t n) {
       // A pair of steps must not pass over a checkpoint time of the recorded window, nor
       // over its end while keeping moments.
       const int64_t mid = c->time + 1;
-      if (fused && n - k >= 2 && !(recording && mid < N && mid % c->plan.stride == 0) && !(keep && mid >= N)) {
+      const bool pair =
+          fused && n - k >= 2 && !(recording && mid < N && mid % c->plan.stride == 0) && !(keep && mid >= N);
+      // A step that ends at a later checkpoint time of the window writes into its slot (never
+      // while keeping moments: the last segment holds no further checkpoint time).
+      const int64_t end = c->time + (pair ? 2 : 1);
+      const bool into_ckpt = recording && end < N && end % c->plan.stride == 0;
+      if (into_ckpt) {
+        s = step_into_ckpt(c, pair ? 2 : 1, end / c->plan.stride);
+        if (s != LBM_OK) return s;
+        k += pair ? 2 : 1;
+        continue;
+      }
+      if (pair) {
         const int64_t j = c->time - t_last;
         s = keep ? do_step2(c, c->state(), 1 - c->cur, c->rec_slot(j), c->rec_slot(j + 1))
                  : do_step2(c, c->state(), 1 - c->cur, nullptr, nullptr);
@@ -470,7 +518,7 @@ lbm_status lbm_step(lbm_ctx* c, int64_t n) {
         k += 2;
         continue;
       }
-      if (small && !recording && n - k >= kGraphSteps) {
+      if (small && !recording && c->state_slot < 0 && n - k >= kGraphSteps) {
         hipGraphExec_t ge = nullptr;
         s = step_graph(c, &ge);
         if (s != LBM_OK) return s;
@@ -527,6 +575,11 @@ lbm_status lbm_set_populations(lbm_ctx* c, const double* d_f) {
     DeviceGuard g(c->device);
     if (c->time != 0) c->rec_valid = false;
     c->last_seg_recorded = false;
+    // The new state goes to a population buffer; a checkpoint slot keeps what it holds.
+    if (c->state_slot >= 0) {
+      c->state_slot = -1;
+      c->cur = 0;
+    }
     return dispatch(c->p.storage, [&](auto eng) -> lbm_status {
       using E = decltype(eng);
       hipError_t e = E::set(c->d, c->layout(c->time), c->state(), d_f, c->stream);

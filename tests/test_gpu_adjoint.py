@@ -138,6 +138,31 @@ def test_adjoint_uses_the_forward_runs_last_segment(storage, pattern):
         assert np.max(np.abs(r - results[0])) <= (1e-14 if storage == "f64" else 1e-6) * scale, k
 
 
+@pytest.mark.parametrize("pattern", ["ab", "aa"])
+@pytest.mark.parametrize("storage", ["f32", "bf16"])
+def test_recorded_run_reads_like_an_unrecorded_one(storage, pattern):
+    """A recorded run keeps its state in a checkpoint slot after a step that ends at a
+    checkpoint time (and starts there: the initial state is checkpoint 0). Its populations,
+    moments and invariants read at every stop (several of them checkpoint times) equal an
+    unrecorded run's bit for bit. 512 x 80, N = 12, spacing 3, two steps per launch asked
+    for; stops after 3, 1, 2, 3, 3 and 2 steps (the last one past N)."""
+    import torch
+    nx, ny, th, nu, N = 512, 80, 0.4, 0.02, 12
+    fields = inp.random_fields(nx, ny, seed=35, u_max=0.08)
+    rec = gpu_sim(nx, ny, th, nu, "complete", storage, pattern, fields=fields, record_steps=N, ckpt_stride=3,
+                  two_step=1)
+    ref = gpu_sim(nx, ny, th, nu, "complete", storage, pattern, fields=fields, two_step=1)
+    for n in (0, 3, 1, 2, 3, 3, 2):
+        rec.step(n)
+        ref.step(n)
+        assert np.array_equal(rec.populations().cpu().numpy(), ref.populations().cpu().numpy()), n
+        for a, b in zip(rec.moments(), ref.moments()):
+            assert torch.equal(a, b), n
+        assert rec.invariants() == ref.invariants(), n
+    rec.close()
+    ref.close()
+
+
 @pytest.mark.parametrize("storage", ["f64", "f32"])
 @pytest.mark.parametrize("nx,ny", [(512, 1), (512, 5), (4096, 200)])
 def test_adjoint_pair_over_row_block_heights(storage, nx, ny):
