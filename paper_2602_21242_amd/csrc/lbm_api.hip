@@ -381,6 +381,10 @@ lbm_status sweep(lbm_ctx* c, int* out_b) {
   return LBM_OK;
 }
 
+// True when the reverse sweep will recompute nothing (one segment, its moments kept by the
+// forward run): the state at N is then never touched and needs no saving and restoring.
+bool state_stays(const lbm_ctx* c) { return c->plan.nck == 1 && c->last_seg_recorded; }
+
 lbm_status check_adjoint_ready(const lbm_ctx* c) {
   if (c->p.record_steps <= 0) return fail(LBM_ERR_STATE, "context was created with record_steps = 0");
   if (!c->rec_valid) return fail(LBM_ERR_STATE, "recorded run was invalidated by lbm_set_populations");
@@ -626,7 +630,9 @@ lbm_status lbm_adjoint(lbm_ctx* c, const void* d_rho_bar, const void* d_ux_bar, 
       return fail(LBM_ERR_INVALID_ARGUMENT, "adjoint: velocity adjoint pointers are required");
     DeviceGuard g(c->device);
     const int64_t N = c->p.record_steps;
-    HIP_TRY(hipMemcpyAsync(c->ckpt(c->plan.nck), c->state(), c->plan.pop_bytes, hipMemcpyDeviceToDevice, c->stream));
+    const bool in_place = state_stays(c);
+    if (!in_place)
+      HIP_TRY(hipMemcpyAsync(c->ckpt(c->plan.nck), c->state(), c->plan.pop_bytes, hipMemcpyDeviceToDevice, c->stream));
     return dispatch(c->p.storage, [&](auto eng) -> lbm_status {
       using E = decltype(eng);
       using T = typename E::T;
@@ -640,7 +646,7 @@ lbm_status lbm_adjoint(lbm_ctx* c, const void* d_rho_bar, const void* d_ux_bar, 
       e = E::ic_adjoint(c->d, c->layout(0), c->ckpt(0), static_cast<const T*>(c->fbar(b)), static_cast<T*>(d_ux0_bar),
                         static_cast<T*>(d_uy0_bar), c->stream);
       if (e != hipSuccess) return fail(LBM_ERR_HIP, std::string("initial-condition adjoint launch: ") + hipGetErrorString(e));
-      return restore(c, c->plan.nck, N);
+      return in_place ? LBM_OK : restore(c, c->plan.nck, N);
     });
   });
 }
@@ -654,7 +660,9 @@ lbm_status lbm_adjoint_populations(lbm_ctx* c, const void* d_fbarN, void* d_fbar
     if (!d_fbarN || !d_fbar0) return fail(LBM_ERR_INVALID_ARGUMENT, "adjoint: population pointers are required");
     DeviceGuard g(c->device);
     const int64_t N = c->p.record_steps;
-    HIP_TRY(hipMemcpyAsync(c->ckpt(c->plan.nck), c->state(), c->plan.pop_bytes, hipMemcpyDeviceToDevice, c->stream));
+    const bool in_place = state_stays(c);
+    if (!in_place)
+      HIP_TRY(hipMemcpyAsync(c->ckpt(c->plan.nck), c->state(), c->plan.pop_bytes, hipMemcpyDeviceToDevice, c->stream));
     return dispatch(c->p.storage, [&](auto eng) -> lbm_status {
       using E = decltype(eng);
       using T = typename E::T;
@@ -665,7 +673,7 @@ lbm_status lbm_adjoint_populations(lbm_ctx* c, const void* d_fbarN, void* d_fbar
       if (st != LBM_OK) return st;
       e = E::fbar_export(c->d, static_cast<const T*>(c->fbar(b)), static_cast<T*>(d_fbar0), c->stream);
       if (e != hipSuccess) return fail(LBM_ERR_HIP, std::string("adjoint export launch: ") + hipGetErrorString(e));
-      return restore(c, c->plan.nck, N);
+      return in_place ? LBM_OK : restore(c, c->plan.nck, N);
     });
   });
 }

@@ -128,8 +128,12 @@ def test_adjoint_uses_the_forward_runs_last_segment(storage, pattern):
                           two_step=1)
             for n in pieces:
                 sim.step(n)
+            before = sim.populations().cpu().numpy()
             for _ in range(2):
                 results.append(sim.adjoint_populations(_t(w, dtype)).cpu().numpy())
+                # the state at N is kept in place (one segment) or restored
+                assert np.array_equal(sim.populations().cpu().numpy(), before), stride
+                assert sim.time == N
             sim.close()
     scale = np.max(np.abs(ref))
     for k, r in enumerate(results):
