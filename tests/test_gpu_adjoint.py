@@ -167,6 +167,48 @@ def test_recorded_run_reads_like_an_unrecorded_one(storage, pattern):
     ref.close()
 
 
+@pytest.mark.parametrize("nx,ny,pattern", [(512, 80, "ab"), (512, 80, "aa"), (64, 16, "ab")])
+def test_recorded_runs_in_random_pieces(nx, ny, pattern):
+    """Checkpoint slots, the kept last segment and the placement of two-step launches
+    depend on how a recorded run is cut into lbm_step calls. N = 13, spacings 1, 2, 3, 5, 7
+    and 13, each run cut into seeded random pieces (some of length 0, the last past N):
+    populations at every stop equal an unrecorded run's bit for bit, and the population
+    adjoint equals that of the same run stepped in one call to 1e-14 (FP64). 512 x 80 takes
+    two steps per launch (A-B); 64 x 16 runs single steps only (rows too short for the
+    two-step kernel)."""
+    import torch
+    th, nu, N = 0.4, 0.02, 13
+    rng = np.random.default_rng(36)
+    fields = inp.random_fields(nx, ny, seed=37, u_max=0.08)
+    w = _t(inp.random_direction((9, ny, nx), seed=38))
+    ref = gpu_sim(nx, ny, th, nu, "complete", "f64", pattern, fields=fields, two_step=1)
+    ref_states = {0: ref.populations().cpu().numpy()}
+    for t in range(1, N + 4):
+        ref.step(1)
+        ref_states[t] = ref.populations().cpu().numpy()
+    ref.close()
+    for stride in (1, 2, 3, 5, 7, 13):
+        one = gpu_sim(nx, ny, th, nu, "complete", "f64", pattern, fields=fields, record_steps=N, ckpt_stride=stride,
+                      two_step=1)
+        one.step(N)
+        want = one.adjoint_populations(w).cpu().numpy()
+        one.close()
+        sim = gpu_sim(nx, ny, th, nu, "complete", "f64", pattern, fields=fields, record_steps=N, ckpt_stride=stride,
+                      two_step=1)
+        t = 0
+        while t < N:
+            n = int(rng.integers(0, 5))
+            n = min(n, N - t) if rng.random() < 0.8 else n  # now and then run past N
+            sim.step(n)
+            t += n
+            assert np.array_equal(sim.populations().cpu().numpy(), ref_states[t]), (stride, t)
+        if t == N:
+            got = sim.adjoint_populations(w).cpu().numpy()
+            assert np.max(np.abs(got - want)) <= 1e-14 * np.max(np.abs(want)), stride
+            assert np.array_equal(sim.populations().cpu().numpy(), ref_states[N]), stride
+        sim.close()
+
+
 @pytest.mark.parametrize("storage", ["f64", "f32"])
 @pytest.mark.parametrize("nx,ny", [(512, 1), (512, 5), (4096, 200)])
 def test_adjoint_pair_over_row_block_heights(storage, nx, ny):
