@@ -247,15 +247,17 @@ __device__ __forceinline__ void xcd_tile(int& bx, int& by) {
   by = t / nx;
 }
 
-// Whether the two-step kernel loads with the nontemporal hint. Without it, the groups a block
-// re-reads as halo stay in L2 for the neighbouring block that reads them too. Measured on
-// MI355X, complete model, HBM bytes read per node and launch with / without the hint: FP64
-// 83.0 / 73.4 (8192^2), BF16 21.8 / 19.4, FP32 38.1 / 37.0 (4096^2); GLUPS: FP64 76.3 ->
-// 79.2, 16-bit unchanged (188), FP32 145.6 -> 144.4 (LBGK 155.3 -> 157.8). FP32 keeps it.
+// Whether the two-step kernel's interior wavefronts load with the nontemporal hint. Without
+// it, the groups a block re-reads as halo stay in L2 for the neighbouring block that reads
+// them too. Measured on MI355X, complete model, HBM bytes read per node and launch with /
+// without the hint: FP64 83.0 / 73.4 (8192^2), BF16 21.8 / 19.4, FP32 38.1 / 37.0 (4096^2);
+// GLUPS: FP64 76.3 -> 79.2, 16-bit unchanged (188), FP32 145.6 -> 144.4 (LBGK 155.3 ->
+// 157.8). So FP32 interior wavefronts keep it; its halo wavefronts, which only load, load
+// plain (140.4 -> 141.6 at 4096^2, 141.1 -> 143.1 at 8192^2, LBGK +1 %).
 template <class S> struct PairLoadsNT : std::false_type {};
 template <> struct PairLoadsNT<float> : std::true_type {};
 
-template <class S>
+template <class S, bool NT = PairLoadsNT<S>::value>
 __device__ __forceinline__ void load_pulled(const S* src, const Geo& geo, int r, const RowPos& rp,
                                             typename StorageTraits<S>::Raw gs[Q]) {
   const int y = r < 0 ? r + geo.ny : (r >= geo.ny ? r - geo.ny : r);
@@ -266,7 +268,7 @@ __device__ __forceinline__ void load_pulled(const S* src, const Geo& geo, int r,
                        reinterpret_cast<const char*>(src) + yp * rsb};
   static_for<0, Q>([&](auto I) {
     constexpr int i = decltype(I)::value;
-    gs[i] = ld_raw<S, PairLoadsNT<S>::value>(at<S>(sr[-cy(i) + 1] + i * psb, rp.template of<-cx(i)>()));
+    gs[i] = ld_raw<S, NT>(at<S>(sr[-cy(i) + 1] + i * psb, rp.template of<-cx(i)>()));
   });
 }
 
@@ -348,21 +350,25 @@ k_step2(const S* __restrict__ src, S* __restrict__ dst, Geo geo, Coef<typename S
     for (int i = 0; i < Q; ++i) st1(at<S>(drow + i * psb, pb), Tr::store(out[i]));
   };
   auto load = [&](const int r) { load_pulled<S>(src, geo, r, ra, gs); };
+  auto load_plain = [&](const int r) { load_pulled<S, false>(src, geo, r, ra, gs); };
 
   // Per row r = y0 - 1 .. y1 every wavefront runs phase A of r, issues the loads of r + 1,
   // and passes two barriers; between them the interior wavefronts run phase B of r - 1
   // (from r = y0 + 1 on). That is 2 (y1 - y0) + 4 barriers for every wavefront.
-  load(y0 - 1);
+  // Plain loads here: this loop runs every wavefront of the unrotated types (whose
+  // PairLoadsNT is false) and only the halo wavefronts of FP32.
   if (!RotatedFuseLoop<S>::value || !interior) {
+    load_plain(y0 - 1);
     for (int r = y0 - 1; r <= y1; ++r) {
       phase_a(r);
-      if (r < y1) load(r + 1);
+      if (r < y1) load_plain(r + 1);
       __syncthreads();
       if (interior && r > y0) phase_b(r - 1);
       __syncthreads();
     }
     return;
   }
+  load(y0 - 1);
   // Interior wavefronts, rotated: the same sequence, with the loop entered right after the
   // loads of the next row. Vector-memory operations complete in issue order, and on every
   // path into the loop those loads are the most recent ones; so phase A, which needs only
