@@ -205,18 +205,59 @@ k_reduce_final(const double* partial, int nparts, double mass_offset, double* re
 
 // Adjoint seed: fbar^N_i = rho_bar + u_bar . (c_i - u)/rho (derivative of rho and
 // u = sum c f / rho with respect to f_i), written to fbar (population layout, compute type).
+// The seed and initial-condition kernels exchange the dense [ny][nx] fields through LDS: a
+// block takes kTileGroups groups of one row (one wavefront per group, lane l holding node
+// x = l S + s as in the storage layout), and the dense entries of those nodes -- kTileGroups
+// consecutive x per lane -- are read or written by consecutive threads. (Indexing the dense
+// fields by each thread's own node strides a wavefront's accesses by S elements.)
+constexpr int kTileGroups = kBlock / kLanes;
+inline dim3 tile_grid(const RunDesc& d) {
+  const int S = d.pitch / kLanes;
+  return dim3(unsigned((S + kTileGroups - 1) / kTileGroups), unsigned(std::min(d.ny, kRowsY)),
+              unsigned((d.ny + kRowsY - 1) / kRowsY));
+}
+// A block's row y, its first group s0 and the group count S; for the thread's dense entry
+// the lane lt, the group offset jt and the node x (-1 outside the row or in the padding).
+struct Tile {
+  int y, s0, S, lt, jt, xt;
+};
+__device__ __forceinline__ Tile tile_of(const RunDesc& d) {
+  Tile t;
+  t.y = int(blockIdx.z) * kRowsY + int(blockIdx.y);
+  t.S = d.pitch / kLanes;
+  t.s0 = int(blockIdx.x) * kTileGroups;
+  t.lt = int(threadIdx.x) / kTileGroups;
+  t.jt = int(threadIdx.x) % kTileGroups;
+  const int x = t.lt * t.S + t.s0 + t.jt;
+  t.xt = (t.s0 + t.jt < t.S && x < d.nx) ? x : -1;
+  return t;
+}
+
+// Seed of the reverse sweep: fbar^N_i = rho_bar + (u_bar . (c_i - u)) / rho, the adjoint of
+// the moments (rho, u) at t = N with respect to the populations.
 template <class S, class T>
 __global__ void __launch_bounds__(kBlock)
 k_seed(const S* buf, RunDesc d, LayoutSel L, const T* rhob, const T* uxb, const T* uyb, T* fbar) {
-  int y, q, x;
-  if (!storage_node(int64_t(blockIdx.x) * kBlock + threadIdx.x, d, y, q, x)) return;
-  const int64_t n = int64_t(y) * d.nx + x;
+  __shared__ T sh[3][kTileGroups][kLanes];
+  const Tile tl = tile_of(d);
+  if (tl.y >= d.ny) return;  // whole block
+  if (tl.xt >= 0) {
+    const int64_t n = int64_t(tl.y) * d.nx + tl.xt;
+    sh[0][tl.jt][tl.lt] = rhob ? rhob[n] : T(0);
+    sh[1][tl.jt][tl.lt] = uxb[n];
+    sh[2][tl.jt][tl.lt] = uyb[n];
+  }
+  __syncthreads();
+  const int w = int(threadIdx.x) / kLanes, lane = int(threadIdx.x) % kLanes;
+  const int s = tl.s0 + w, x = lane * tl.S + s, y = tl.y;
+  if (s >= tl.S || x >= d.nx) return;
+  const int q = s * kLanes + lane;
   double drho, jx, jy;
   node_moments(buf, d, L, x, y, drho, jx, jy);
   const T r = T(d.rho0 + drho);
   const T vx = T(jx / (d.rho0 + drho)), vy = T(jy / (d.rho0 + drho));
-  const T rb = rhob ? rhob[n] : T(0);
-  const T ax = uxb[n] / r, ay = uyb[n] / r;
+  const T rb = sh[0][w][lane];
+  const T ax = sh[1][w][lane] / r, ay = sh[2][w][lane] / r;
 #pragma unroll
   for (int i = 0; i < Q; ++i)
     fbar[local_index(i, q, y, d)] = rb + ax * (T(cx(i)) - vx) + ay * (T(cy(i)) - vy);
@@ -248,28 +289,39 @@ __global__ void __launch_bounds__(kBlock) k_fbar_export(RunDesc d, const T* fbar
 template <class S, class T>
 __global__ void __launch_bounds__(kBlock)
 k_ic_adjoint(const S* buf0, RunDesc d, LayoutSel L, const T* fbar, T* uxb, T* uyb) {
-  int y, q, x;
-  if (!storage_node(int64_t(blockIdx.x) * kBlock + threadIdx.x, d, y, q, x)) return;
-  const int64_t n = int64_t(y) * d.nx + x;
-  double drho, jx, jy;
-  node_moments(buf0, d, L, x, y, drho, jx, jy);
-  const T r = T(d.rho0 + drho);
-  const T vx = T(jx / (d.rho0 + drho)), vy = T(jy / (d.rho0 + drho));
-  const T th = T(d.theta);
-  const T hx[3] = {T(0.5) * (th + vx * vx - vx), T(1) - th - vx * vx, T(0.5) * (th + vx * vx + vx)};
-  const T hy[3] = {T(0.5) * (th + vy * vy - vy), T(1) - th - vy * vy, T(0.5) * (th + vy * vy + vy)};
-  const T gx[3] = {vx - T(0.5), T(-2) * vx, vx + T(0.5)};
-  const T gy[3] = {vy - T(0.5), T(-2) * vy, vy + T(0.5)};
-  T ax = T(0), ay = T(0);
+  __shared__ T sh[2][kTileGroups][kLanes];
+  const Tile tl = tile_of(d);
+  if (tl.y >= d.ny) return;  // whole block
+  const int w = int(threadIdx.x) / kLanes, lane = int(threadIdx.x) % kLanes;
+  const int s = tl.s0 + w, x = lane * tl.S + s, y = tl.y;
+  if (s < tl.S && x < d.nx) {
+    const int q = s * kLanes + lane;
+    double drho, jx, jy;
+    node_moments(buf0, d, L, x, y, drho, jx, jy);
+    const T r = T(d.rho0 + drho);
+    const T vx = T(jx / (d.rho0 + drho)), vy = T(jy / (d.rho0 + drho));
+    const T th = T(d.theta);
+    const T hx[3] = {T(0.5) * (th + vx * vx - vx), T(1) - th - vx * vx, T(0.5) * (th + vx * vx + vx)};
+    const T hy[3] = {T(0.5) * (th + vy * vy - vy), T(1) - th - vy * vy, T(0.5) * (th + vy * vy + vy)};
+    const T gx[3] = {vx - T(0.5), T(-2) * vx, vx + T(0.5)};
+    const T gy[3] = {vy - T(0.5), T(-2) * vy, vy + T(0.5)};
+    T ax = T(0), ay = T(0);
 #pragma unroll
-  for (int i = 0; i < Q; ++i) {
-    const int a = cx(i) + 1, b = cy(i) + 1;
-    const T fb = fbar[local_index(i, q, y, d)];
-    ax += fb * r * gx[a] * hy[b];
-    ay += fb * r * hx[a] * gy[b];
+    for (int i = 0; i < Q; ++i) {
+      const int a = cx(i) + 1, b = cy(i) + 1;
+      const T fb = fbar[local_index(i, q, y, d)];
+      ax += fb * r * gx[a] * hy[b];
+      ay += fb * r * hx[a] * gy[b];
+    }
+    sh[0][w][lane] = ax;
+    sh[1][w][lane] = ay;
   }
-  uxb[n] = ax;
-  uyb[n] = ay;
+  __syncthreads();
+  if (tl.xt >= 0) {
+    const int64_t n = int64_t(y) * d.nx + tl.xt;
+    uxb[n] = sh[0][tl.jt][tl.lt];
+    uyb[n] = sh[1][tl.jt][tl.lt];
+  }
 }
 
 // --- step dispatch ---------------------------------------------------------------------------
@@ -465,8 +517,8 @@ hipError_t Engine<S>::invariants(const RunDesc& d, LayoutSel L, const void* buf,
 template <class S>
 hipError_t Engine<S>::seed(const RunDesc& d, LayoutSel L, const void* buf, const T* rhob, const T* uxb, const T* uyb,
                            T* fbar, hipStream_t st) {
-  hipLaunchKernelGGL((k_seed<S, T>), dim3(node_blocks(d)), dim3(kBlock), 0, st, static_cast<const S*>(buf), d, L, rhob,
-                     uxb, uyb, fbar);
+  hipLaunchKernelGGL((k_seed<S, T>), tile_grid(d), dim3(kBlock), 0, st, static_cast<const S*>(buf), d, L, rhob, uxb,
+                     uyb, fbar);
   return hipGetLastError();
 }
 
@@ -515,8 +567,8 @@ hipError_t Engine<S>::adjoint_step(const RunDesc& d, const T* fbar_next, T* fbar
 template <class S>
 hipError_t Engine<S>::ic_adjoint(const RunDesc& d, LayoutSel L, const void* buf0, const T* fbar, T* uxb, T* uyb,
                                  hipStream_t st) {
-  hipLaunchKernelGGL((k_ic_adjoint<S, T>), dim3(node_blocks(d)), dim3(kBlock), 0, st, static_cast<const S*>(buf0), d, L,
-                     fbar, uxb, uyb);
+  hipLaunchKernelGGL((k_ic_adjoint<S, T>), tile_grid(d), dim3(kBlock), 0, st, static_cast<const S*>(buf0), d, L, fbar,
+                     uxb, uyb);
   return hipGetLastError();
 }
 
