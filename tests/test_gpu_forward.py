@@ -172,6 +172,7 @@ FULL = [
     ("tg4096", "complete", "f32", "aa"), ("turb8192", "complete", "f16", "aa"), ("turb8192", "complete", "f16", "ab"),
     ("turb8192", "complete", "bf16", "ab"),
     ("turb8192", "complete", "f64", "ab"), ("dsl16384", "complete", "f32", "aa"),
+    ("dsl16384", "complete", "f32", "ab"), ("turb8192", "bgk", "f16", "ab"),
 ]
 
 
