@@ -59,17 +59,56 @@ __device__ __forceinline__ int64_t local_index(int i, int q, int y, const RunDes
 
 // --- per-node auxiliary kernels --------------------------------------------------------------
 
+// The per-node auxiliary kernels exchange the dense [ny][nx] fields through LDS: a
+// block takes kTileGroups groups of one row (one wavefront per group, lane l holding node
+// x = l S + s as in the storage layout), and the dense entries of those nodes -- kTileGroups
+// consecutive x per lane -- are read or written by consecutive threads. (Indexing the dense
+// fields by each thread's own node strides a wavefront's accesses by S elements.)
+constexpr int kTileGroups = kBlock / kLanes;
+inline dim3 tile_grid(const RunDesc& d) {
+  const int S = d.pitch / kLanes;
+  return dim3(unsigned((S + kTileGroups - 1) / kTileGroups), unsigned(std::min(d.ny, kRowsY)),
+              unsigned((d.ny + kRowsY - 1) / kRowsY));
+}
+// A block's row y, its first group s0 and the group count S; for the thread's dense entry
+// the lane lt, the group offset jt and the node x (-1 outside the row or in the padding).
+struct Tile {
+  int y, s0, S, lt, jt, xt;
+};
+__device__ __forceinline__ Tile tile_of(const RunDesc& d) {
+  Tile t;
+  t.y = int(blockIdx.z) * kRowsY + int(blockIdx.y);
+  t.S = d.pitch / kLanes;
+  t.s0 = int(blockIdx.x) * kTileGroups;
+  t.lt = int(threadIdx.x) / kTileGroups;
+  t.jt = int(threadIdx.x) % kTileGroups;
+  const int x = t.lt * t.S + t.s0 + t.jt;
+  t.xt = (t.s0 + t.jt < t.S && x < d.nx) ? x : -1;
+  return t;
+}
+
+
 // f^0 = f^eq(rho, u) of the guided equilibrium (eq:guidedEq), stored shifted, computed in FP64
 // as drho Phi_x Phi_y + rho0 (d_x Phi_y + r_x d_y) (no cancellation against w_i rho0).
 template <class S>
 __global__ void __launch_bounds__(kBlock)
 k_init(S* buf, RunDesc d, LayoutSel L, const double* rho, const double* ux, const double* uy) {
   using Tr = StorageTraits<S>;
-  int y, q, x;
-  if (!storage_node(int64_t(blockIdx.x) * kBlock + threadIdx.x, d, y, q, x)) return;
-  const int64_t n = int64_t(y) * d.nx + x;
-  const double r = rho ? rho[n] : d.rho0;
-  const double vx = ux[n], vy = uy[n];
+  __shared__ double sh[3][kTileGroups][kLanes];
+  const Tile tl = tile_of(d);
+  if (tl.y >= d.ny) return;  // whole block
+  if (tl.xt >= 0) {
+    const int64_t n = int64_t(tl.y) * d.nx + tl.xt;
+    sh[0][tl.jt][tl.lt] = rho ? rho[n] : d.rho0;
+    sh[1][tl.jt][tl.lt] = ux[n];
+    sh[2][tl.jt][tl.lt] = uy[n];
+  }
+  __syncthreads();
+  const int w = int(threadIdx.x) / kLanes, lane = int(threadIdx.x) % kLanes;
+  const int s = tl.s0 + w, x = lane * tl.S + s, y = tl.y;
+  if (s >= tl.S || x >= d.nx) return;
+  const double r = sh[0][w][lane];
+  const double vx = sh[1][w][lane], vy = sh[2][w][lane];
   const double drho = r - d.rho0;
   const double th = d.theta;
   const double dx[3] = {0.5 * (vx * vx - vx), -vx * vx, 0.5 * (vx * vx + vx)};
@@ -88,16 +127,26 @@ template <class S, class O>
 __global__ void __launch_bounds__(kBlock)
 k_get(const S* buf, RunDesc d, LayoutSel L, O* out) {
   using Tr = StorageTraits<S>;
+  __shared__ O sh[Q][kTileGroups][kLanes];
   const int64_t N = int64_t(d.nx) * d.ny;
-  int y, q, x;
-  if (!storage_node(int64_t(blockIdx.x) * kBlock + threadIdx.x, d, y, q, x)) return;
-  const int64_t n = int64_t(y) * d.nx + x;
-  const double th = d.theta;
+  const Tile tl = tile_of(d);
+  if (tl.y >= d.ny) return;  // whole block
+  const int w = int(threadIdx.x) / kLanes, lane = int(threadIdx.x) % kLanes;
+  const int s = tl.s0 + w, x = lane * tl.S + s, y = tl.y;
+  if (s < tl.S && x < d.nx) {
+    const double th = d.theta;
 #pragma unroll
-  for (int i = 0; i < Q; ++i) {
-    const double w = (cx(i) == 0 ? 1.0 - th : 0.5 * th) * (cy(i) == 0 ? 1.0 - th : 0.5 * th);
-    const double g = double(Tr::load(buf[layout_index(i, x, y, d, L)]));
-    out[i * N + n] = O(g + w * d.rho0);
+    for (int i = 0; i < Q; ++i) {
+      const double wt = (cx(i) == 0 ? 1.0 - th : 0.5 * th) * (cy(i) == 0 ? 1.0 - th : 0.5 * th);
+      const double g = double(Tr::load(buf[layout_index(i, x, y, d, L)]));
+      sh[i][w][lane] = O(g + wt * d.rho0);
+    }
+  }
+  __syncthreads();
+  if (tl.xt >= 0) {
+    const int64_t n = int64_t(y) * d.nx + tl.xt;
+#pragma unroll
+    for (int i = 0; i < Q; ++i) out[i * N + n] = sh[i][tl.jt][tl.lt];
   }
 }
 
@@ -105,15 +154,24 @@ template <class S>
 __global__ void __launch_bounds__(kBlock)
 k_set(S* buf, RunDesc d, LayoutSel L, const double* in) {
   using Tr = StorageTraits<S>;
+  __shared__ double sh[Q][kTileGroups][kLanes];
   const int64_t N = int64_t(d.nx) * d.ny;
-  int y, q, x;
-  if (!storage_node(int64_t(blockIdx.x) * kBlock + threadIdx.x, d, y, q, x)) return;
-  const int64_t n = int64_t(y) * d.nx + x;
+  const Tile tl = tile_of(d);
+  if (tl.y >= d.ny) return;  // whole block
+  if (tl.xt >= 0) {
+    const int64_t n = int64_t(tl.y) * d.nx + tl.xt;
+#pragma unroll
+    for (int i = 0; i < Q; ++i) sh[i][tl.jt][tl.lt] = in[i * N + n];
+  }
+  __syncthreads();
+  const int w = int(threadIdx.x) / kLanes, lane = int(threadIdx.x) % kLanes;
+  const int s = tl.s0 + w, x = lane * tl.S + s, y = tl.y;
+  if (s >= tl.S || x >= d.nx) return;
   const double th = d.theta;
 #pragma unroll
   for (int i = 0; i < Q; ++i) {
-    const double w = (cx(i) == 0 ? 1.0 - th : 0.5 * th) * (cy(i) == 0 ? 1.0 - th : 0.5 * th);
-    buf[layout_index(i, x, y, d, L)] = Tr::store(typename Tr::T(in[i * N + n] - w * d.rho0));
+    const double wt = (cx(i) == 0 ? 1.0 - th : 0.5 * th) * (cy(i) == 0 ? 1.0 - th : 0.5 * th);
+    buf[layout_index(i, x, y, d, L)] = Tr::store(typename Tr::T(sh[i][w][lane] - wt * d.rho0));
   }
 }
 
@@ -138,15 +196,26 @@ __device__ __forceinline__ void node_moments(const S* buf, const RunDesc& d, Lay
 template <class S, class O>
 __global__ void __launch_bounds__(kBlock)
 k_moments(const S* buf, RunDesc d, LayoutSel L, O* rho, O* ux, O* uy) {
-  int y, q, x;
-  if (!storage_node(int64_t(blockIdx.x) * kBlock + threadIdx.x, d, y, q, x)) return;
-  const int64_t n = int64_t(y) * d.nx + x;
-  double drho, jx, jy;
-  node_moments(buf, d, L, x, y, drho, jx, jy);
-  const double r = d.rho0 + drho;
-  if (rho) rho[n] = O(r);
-  if (ux) ux[n] = O(jx / r);
-  if (uy) uy[n] = O(jy / r);
+  __shared__ O sh[3][kTileGroups][kLanes];
+  const Tile tl = tile_of(d);
+  if (tl.y >= d.ny) return;  // whole block
+  const int w = int(threadIdx.x) / kLanes, lane = int(threadIdx.x) % kLanes;
+  const int s = tl.s0 + w, x = lane * tl.S + s, y = tl.y;
+  if (s < tl.S && x < d.nx) {
+    double drho, jx, jy;
+    node_moments(buf, d, L, x, y, drho, jx, jy);
+    const double r = d.rho0 + drho;
+    sh[0][w][lane] = O(r);
+    sh[1][w][lane] = O(jx / r);
+    sh[2][w][lane] = O(jy / r);
+  }
+  __syncthreads();
+  if (tl.xt >= 0) {
+    const int64_t n = int64_t(y) * d.nx + tl.xt;
+    if (rho) rho[n] = sh[0][tl.jt][tl.lt];
+    if (ux) ux[n] = sh[1][tl.jt][tl.lt];
+    if (uy) uy[n] = sh[2][tl.jt][tl.lt];
+  }
 }
 
 // FP64 totals, first stage: fixed grid of kReduceBlocks blocks, deterministic order.
@@ -205,34 +274,6 @@ k_reduce_final(const double* partial, int nparts, double mass_offset, double* re
 
 // Adjoint seed: fbar^N_i = rho_bar + u_bar . (c_i - u)/rho (derivative of rho and
 // u = sum c f / rho with respect to f_i), written to fbar (population layout, compute type).
-// The seed and initial-condition kernels exchange the dense [ny][nx] fields through LDS: a
-// block takes kTileGroups groups of one row (one wavefront per group, lane l holding node
-// x = l S + s as in the storage layout), and the dense entries of those nodes -- kTileGroups
-// consecutive x per lane -- are read or written by consecutive threads. (Indexing the dense
-// fields by each thread's own node strides a wavefront's accesses by S elements.)
-constexpr int kTileGroups = kBlock / kLanes;
-inline dim3 tile_grid(const RunDesc& d) {
-  const int S = d.pitch / kLanes;
-  return dim3(unsigned((S + kTileGroups - 1) / kTileGroups), unsigned(std::min(d.ny, kRowsY)),
-              unsigned((d.ny + kRowsY - 1) / kRowsY));
-}
-// A block's row y, its first group s0 and the group count S; for the thread's dense entry
-// the lane lt, the group offset jt and the node x (-1 outside the row or in the padding).
-struct Tile {
-  int y, s0, S, lt, jt, xt;
-};
-__device__ __forceinline__ Tile tile_of(const RunDesc& d) {
-  Tile t;
-  t.y = int(blockIdx.z) * kRowsY + int(blockIdx.y);
-  t.S = d.pitch / kLanes;
-  t.s0 = int(blockIdx.x) * kTileGroups;
-  t.lt = int(threadIdx.x) / kTileGroups;
-  t.jt = int(threadIdx.x) % kTileGroups;
-  const int x = t.lt * t.S + t.s0 + t.jt;
-  t.xt = (t.s0 + t.jt < t.S && x < d.nx) ? x : -1;
-  return t;
-}
-
 // Seed of the reverse sweep: fbar^N_i = rho_bar + (u_bar . (c_i - u)) / rho, the adjoint of
 // the moments (rho, u) at t = N with respect to the populations.
 template <class S, class T>
@@ -469,24 +510,24 @@ hipError_t Engine<S>::step2(const RunDesc& d, const void* src, void* dst, void* 
 template <class S>
 hipError_t Engine<S>::init(const RunDesc& d, LayoutSel L, void* buf, const double* rho, const double* ux,
                            const double* uy, hipStream_t st) {
-  hipLaunchKernelGGL(k_init<S>, dim3(node_blocks(d)), dim3(kBlock), 0, st, static_cast<S*>(buf), d, L, rho, ux, uy);
+  hipLaunchKernelGGL(k_init<S>, tile_grid(d), dim3(kBlock), 0, st, static_cast<S*>(buf), d, L, rho, ux, uy);
   return hipGetLastError();
 }
 
 template <class S>
 hipError_t Engine<S>::get(const RunDesc& d, LayoutSel L, const void* buf, bool out_f64, void* out, hipStream_t st) {
   if (out_f64)
-    hipLaunchKernelGGL((k_get<S, double>), dim3(node_blocks(d)), dim3(kBlock), 0, st, static_cast<const S*>(buf), d, L,
+    hipLaunchKernelGGL((k_get<S, double>), tile_grid(d), dim3(kBlock), 0, st, static_cast<const S*>(buf), d, L,
                        static_cast<double*>(out));
   else
-    hipLaunchKernelGGL((k_get<S, float>), dim3(node_blocks(d)), dim3(kBlock), 0, st, static_cast<const S*>(buf), d, L,
+    hipLaunchKernelGGL((k_get<S, float>), tile_grid(d), dim3(kBlock), 0, st, static_cast<const S*>(buf), d, L,
                        static_cast<float*>(out));
   return hipGetLastError();
 }
 
 template <class S>
 hipError_t Engine<S>::set(const RunDesc& d, LayoutSel L, void* buf, const double* in, hipStream_t st) {
-  hipLaunchKernelGGL(k_set<S>, dim3(node_blocks(d)), dim3(kBlock), 0, st, static_cast<S*>(buf), d, L, in);
+  hipLaunchKernelGGL(k_set<S>, tile_grid(d), dim3(kBlock), 0, st, static_cast<S*>(buf), d, L, in);
   return hipGetLastError();
 }
 
@@ -494,10 +535,10 @@ template <class S>
 hipError_t Engine<S>::moments(const RunDesc& d, LayoutSel L, const void* buf, bool out_f64, void* rho, void* ux,
                               void* uy, hipStream_t st) {
   if (out_f64)
-    hipLaunchKernelGGL((k_moments<S, double>), dim3(node_blocks(d)), dim3(kBlock), 0, st, static_cast<const S*>(buf), d,
+    hipLaunchKernelGGL((k_moments<S, double>), tile_grid(d), dim3(kBlock), 0, st, static_cast<const S*>(buf), d,
                        L, static_cast<double*>(rho), static_cast<double*>(ux), static_cast<double*>(uy));
   else
-    hipLaunchKernelGGL((k_moments<S, float>), dim3(node_blocks(d)), dim3(kBlock), 0, st, static_cast<const S*>(buf), d,
+    hipLaunchKernelGGL((k_moments<S, float>), tile_grid(d), dim3(kBlock), 0, st, static_cast<const S*>(buf), d,
                        L, static_cast<float*>(rho), static_cast<float*>(ux), static_cast<float*>(uy));
   return hipGetLastError();
 }
