@@ -82,12 +82,32 @@ def make_sim(w, model, storage, pattern, fields, **kw):
                       pattern=pattern, **kw)
 
 
-def time_steps(sim, steps, warmup):
-    """Average milliseconds per step over `steps` steps after `warmup` untimed ones, HIP events
-    recorded on the stream the library launches on."""
+def spin_up(sim, seconds):
+    """Keep the GPU busy with steps of `sim` (a throwaway context) for about `seconds`, and
+    return with a last chunk still queued, so that work enqueued next starts without an idle
+    gap. The GPU's clocks change after every idle period: the first milliseconds of a burst of
+    two-step launches run fast, the next 15-20 ms up to 1.5x slower, then the launches settle
+    (measured per launch on MI355X), and only the steady state says what a long run gets."""
     import torch
+    chunk = 16 * sim.steps_per_launch
+    t0 = time.perf_counter()
+    while time.perf_counter() - t0 < seconds:
+        sim.step(chunk)
+        torch.cuda.synchronize()
+    sim.step(chunk)
+
+
+def time_steps(sim, steps, warmup, spin=None, spin_s=0.0):
+    """Average milliseconds per step over `steps` steps after `warmup` untimed ones, HIP events
+    recorded on the stream the library launches on. With `spin` (another context on the same
+    stream) the GPU first runs that context for about spin_s seconds, then the warm-up and the
+    timed steps follow without a pause."""
+    import torch
+    if spin is not None:
+        spin_up(spin, spin_s)
+    else:
+        torch.cuda.synchronize()
     sim.step(warmup)
-    torch.cuda.synchronize()
     start = torch.cuda.Event(enable_timing=True)
     stop = torch.cuda.Event(enable_timing=True)
     start.record(sim.stream)
@@ -97,12 +117,28 @@ def time_steps(sim, steps, warmup):
     return start.elapsed_time(stop) / steps
 
 
-def time_single_steps(sim, steps, warmup):
+def time_steady(sim, steps, spin_s=0.2):
+    """Milliseconds per step of `sim` in the steady state: its own steps for about spin_s
+    seconds, then `steps` timed steps without a pause (the variants, which have no fixed
+    warm-up count)."""
+    return time_steps(sim, steps, 0, spin=sim, spin_s=spin_s)
+
+
+def time_single_steps(sim, steps, warmup, spin=None, spin_s=0.0):
     """Like time_steps, with one lbm_step(1) call per step (always the single-step kernel)."""
     import torch
+    if spin is not None:
+        t0 = time.perf_counter()
+        while time.perf_counter() - t0 < spin_s:
+            for _ in range(16):
+                spin.step(1)
+            torch.cuda.synchronize()
+        for _ in range(16):
+            spin.step(1)
+    else:
+        torch.cuda.synchronize()
     for _ in range(warmup):
         sim.step(1)
-    torch.cuda.synchronize()
     start = torch.cuda.Event(enable_timing=True)
     stop = torch.cuda.Event(enable_timing=True)
     start.record(sim.stream)
@@ -178,8 +214,11 @@ def main():
     ap.add_argument("--single-step", action="store_true",
                     help="time the headline with one lbm_step(1) call per step (the single-step kernel)")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
-    ap.add_argument("--precision-steps", type=int, default=1000,
-                    help="steps of the 8192^2 storage-precision comparison")
+    ap.add_argument("--no-dsl", action="store_true", help="skip the 16384 x 4096 double-shear-layer gradient")
+    ap.add_argument("--spin-up", type=float, default=0.25,
+                    help="seconds of steps on a throwaway context right before the headline's warm-up steps")
+    ap.add_argument("--precision-steps", type=int, default=5000,
+                    help="last step of the 8192^2 storage-precision table (also taken at 100 and 1000; 0: skip)")
     ap.add_argument("--only", choices=["adjoint", "precision", "viscosity", "shear-layer", "shocktube"], default=None,
                     help="run only one section and print its JSON (adjoint: sweep and end-to-end gradient; "
                          "precision: storage types on the 8192^2 turbulence workload against the FP64 run; "
@@ -232,19 +271,41 @@ def main():
     log(f"[bench] headline: {w.name} {w.nx}x{w.ny} {args.model} {args.storage} {args.pattern}, "
         f"{args.warmup} warm-up + {args.steps} timed steps")
     fields = w.fields(seed=0)
+    timer = time_single_steps if args.single_step else time_steps
+    # Cold: a fresh context, the warm-up steps and the timed steps right after its creation,
+    # with the clocks wherever the preceding idle period left them.
     sim = make_sim(w, args.model, args.storage, args.pattern, fields)
+    cold_ms = timer(sim, args.steps, args.warmup)
+    del sim
+    # Steady state: the same on a new context after a spin-up of a throwaway context of the
+    # same configuration, with no pause between the spin-up, the warm-up and the timed steps.
+    sim = make_sim(w, args.model, args.storage, args.pattern, fields)
+    spin = make_sim(w, args.model, args.storage, args.pattern, fields)
     spl = 1 if args.single_step else sim.steps_per_launch
-    ms = (time_single_steps if args.single_step else time_steps)(sim, args.steps, args.warmup)
+    ms = timer(sim, args.steps, args.warmup, spin=spin, spin_s=args.spin_up)
+    del spin
     inv = sim.invariants(allow_nonfinite=True)
     del sim
     glups = nodes / (ms * 1e-3) / 1e9
-    # Algorithmic bytes per launch: one read and one write of the nine populations of every
-    # node, whether the launch advances one step or two (the two-step kernel keeps the
-    # intermediate state in LDS).
-    achieved = ALG_BYTES[args.storage] * nodes / (spl * ms * 1e-3) / 1e9
-    log(f"[bench] {ms:.4f} ms/step ({spl} step(s) per launch), {glups:.2f} GLUPS, {achieved:.0f} GB/s algorithmic")
+    launch_s = spl * ms * 1e-3
+    # Roofline: one read and one write of the nine populations per node update (72 B in FP32)
+    # times the updates of one launch, over the launch time. A launch of the two-step kernel
+    # performs two updates and keeps the intermediate state in LDS, so its own floor is one
+    # read and one write per launch (36 B per update in FP32), reported as pair_floor.
+    achieved = ALG_BYTES[args.storage] * spl * nodes / launch_s / 1e9
+    log(f"[bench] {ms:.4f} ms/step ({spl} step(s) per launch), {glups:.2f} GLUPS "
+        f"(cold {cold_ms:.4f} ms/step, {nodes / (cold_ms * 1e-3) / 1e9:.2f} GLUPS), "
+        f"{achieved:.0f} GB/s algorithmic at {ALG_BYTES[args.storage]} B per node update")
     traffic = load_traffic(w.name, args.model, args.storage, args.pattern)
     kernel = (f"k_step2<{args.storage},{args.model}>" if spl == 2 else f"k_step<{args.storage},{args.model},{args.pattern}>")
+    roofline = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": achieved / HBM_PEAK_GBS, "traffic": traffic, "kernel": kernel, "steps_per_launch": spl,
+                "alg_bytes_per_node_update": ALG_BYTES[args.storage], "launch_us": launch_s * 1e6,
+                "traffic_frac": None if traffic is None else traffic / launch_s / 1e9 / HBM_PEAK_GBS}
+    if spl == 2:
+        floor = ALG_BYTES[args.storage] * nodes / launch_s / 1e9
+        roofline["pair_floor"] = {"bytes_per_node_update": ALG_BYTES[args.storage] // 2, "achieved": floor,
+                                  "frac": floor / HBM_PEAK_GBS}
 
     out = {
         "metric": METRIC, "value": glups, "unit": "GLUPS", "n_gpus": 1, "steps": args.steps,
@@ -254,10 +315,12 @@ def main():
                    "model": args.model, "storage": args.storage, "pattern": args.pattern,
                    "initial_field": "Taylor-Green U0=0.1 + N(0,1e-3^2) velocity noise, seed 0"
                    if w.name == "tg4096" else w.extra},
-        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic, "kernel": kernel,
-                     "steps_per_launch": spl, "alg_bytes_per_node_per_launch": ALG_BYTES[args.storage],
-                     "launch_us": spl * ms * 1e3},
+        "roofline": roofline,
+        "clock": {"spin_up_s": args.spin_up, "cold_ms_per_step": cold_ms,
+                  "cold_GLUPS": nodes / (cold_ms * 1e-3) / 1e9,
+                  "note": "value: timed steps after a spin-up of a throwaway context of the same configuration "
+                          "(steady clocks); cold: the same warm-up and timed steps on a fresh context right "
+                          "after its creation"},
         "mass_after_run": inv[0] if inv else None,
     }
 
@@ -271,50 +334,49 @@ def main():
             log(f"[bench] variant tg4096 {model} f32 {pattern}")
             s = make_sim(w, model, "f32", pattern, fields)
             sp = s.steps_per_launch
-            m = time_steps(s, steps_v, 20)
+            m = time_steady(s, steps_v)
             var[f"tg4096/{model}/f32/{pattern}"] = {"ms_per_step": m, "GLUPS": nodes / (m * 1e-3) / 1e9,
                                                     "steps_per_launch": sp,
-                                                    "hbm_frac": 72 * nodes / (sp * m * 1e-3) / 1e9 / HBM_PEAK_GBS}
+                                                    "hbm_frac_per_update": 72 * nodes / (m * 1e-3) / 1e9 / HBM_PEAK_GBS}
             del s
         # The single-step kernel on the headline workload (one lbm_step(1) call per step).
         log("[bench] variant tg4096 complete f32 ab, one step per launch")
         s = make_sim(w, "complete", "f32", "ab", fields)
-        m = time_single_steps(s, steps_v, 20)
+        m = time_single_steps(s, steps_v, 0, spin=s, spin_s=0.2)
         var["tg4096/complete/f32/ab/single-step-kernel"] = {
             "ms_per_step": m, "GLUPS": nodes / (m * 1e-3) / 1e9, "steps_per_launch": 1,
-            "hbm_frac": 72 * nodes / (m * 1e-3) / 1e9 / HBM_PEAK_GBS}
+            "hbm_frac_per_update": 72 * nodes / (m * 1e-3) / 1e9 / HBM_PEAK_GBS}
         del s
         del fields
-        # Storage types on the 8192^2 turbulence workload, with the error against the FP64 run.
+        # Storage types on the 8192^2 turbulence workload: throughput, and the error table against
+        # the FP64 run after 100, 1000 and 5000 steps.
         wt = inp.WORKLOADS["turb8192"]
         log("[bench] generating turb8192 fields")
         tf = wt.fields(seed=0)
         nt = wt.nx * wt.ny
-        ref = None
         for storage in ("f64", "f32", "f16", "bf16"):
             log(f"[bench] variant turb8192 complete {storage} ab")
             s = make_sim(wt, "complete", storage, "ab", tf)
             sp = s.steps_per_launch
-            m = time_steps(s, 200, 20)
+            m = time_steady(s, 200)
             ent = {"ms_per_step": m, "GLUPS": nt / (m * 1e-3) / 1e9, "steps_per_launch": sp,
-                   "hbm_frac": ALG_BYTES[storage] * nt / (sp * m * 1e-3) / 1e9 / HBM_PEAK_GBS}
+                   "hbm_frac_per_update": ALG_BYTES[storage] * nt / (m * 1e-3) / 1e9 / HBM_PEAK_GBS}
+            if sp == 2:
+                ent["pair_floor_frac"] = ALG_BYTES[storage] * nt / (sp * m * 1e-3) / 1e9 / HBM_PEAK_GBS
             del s
-            if args.precision_steps > 0:
-                s = make_sim(wt, "complete", storage, "ab", tf)
-                s.step(args.precision_steps)
-                f = s.populations(dtype=torch.float64)
-                if storage == "f64":
-                    ref = f
-                    fmax = ref.abs().max().item()
-                else:
-                    ent[f"eps_f_vs_f64_after_{args.precision_steps}"] = (f - ref).abs().max().item() / fmax
-                del s, f
             var[f"turb8192/complete/{storage}/ab"] = ent
-        del ref, tf
-        # Adjoint: the adjoint step kernel at 4096^2 (HBM-bound) and the end-to-end gradient on
-        # the 1024^2 advected shear wave (500 steps, sqrt(N) checkpoints).
+        del tf
+        if args.precision_steps:
+            log("[bench] storage precision on turb8192")
+            var["precision_turb8192"] = bench_precision(inp, checkpoints=(100, 1000, args.precision_steps))
+        # Adjoint: the adjoint kernels at 4096^2 (HBM-sized), the end-to-end gradient on the
+        # 1024^2 advected shear wave (500 steps, sqrt(N) checkpoints) and on the 16384 x 4096
+        # double shear layer (3000 steps, enstrophy gradient).
         log("[bench] adjoint")
         var.update(bench_adjoint(inp))
+        if not args.no_dsl:
+            log("[bench] double shear layer gradient")
+            var.update(bench_gradient_dsl(inp))
         out["variants"] = var
         if not args.no_cpu:
             log("[bench] CPU oracle baseline")
@@ -336,10 +398,11 @@ def shell_spectrum(ux, uy):
     return torch.bincount(K.flatten(), weights=e.flatten()).cpu()
 
 
-def bench_precision(inp, checkpoints=(100, 1000, 5000)):
+def bench_precision(inp, checkpoints=(100, 1000, 5000), storages=("f32", "f16", "bf16")):
     """Storage precision on the 8192^2 decaying-turbulence workload (complete model): errors
     of FP32, FP16 and BF16 storage against the FP64-storage run at the given steps
-    (populations, velocity, density, kinetic energy and the shell energy spectrum)."""
+    (populations, velocity, density, kinetic energy and the shell energy spectrum), all on
+    the device. eps_f = max |f - f_ref| / max |f_ref| over populations and nodes."""
     import torch
     w = inp.WORKLOADS["turb8192"]
     fields = w.fields(seed=0)
@@ -351,12 +414,12 @@ def bench_precision(inp, checkpoints=(100, 1000, 5000)):
         s.step(n - done)
         done = n
         r, ux, uy = s.moments()
-        ref[n] = dict(f=s.populations(dtype=torch.float32).cpu(), rho=r.cpu(), ux=ux.cpu(), uy=uy.cpu(),
+        ref[n] = dict(f=s.populations(dtype=torch.float64), rho=r, ux=ux, uy=uy,
                       ke=float(0.5 * (r * (ux * ux + uy * uy)).sum()), spec=shell_spectrum(ux, uy))
     del s
     out = {"workload": w.name, "model": "complete", "reference": "FP64 storage, FP64 arithmetic",
            "ke_reference": {str(n): ref[n]["ke"] for n in checkpoints}}
-    for storage in ("f32", "f16", "bf16"):
+    for storage in storages:
         log(f"[precision] {storage}")
         s = make_sim(w, "complete", storage, "ab", fields)
         done = 0
@@ -365,7 +428,7 @@ def bench_precision(inp, checkpoints=(100, 1000, 5000)):
             s.step(n - done)
             done = n
             r, ux, uy = s.moments()
-            f = s.populations(dtype=torch.float32).cpu()
+            f = s.populations(dtype=torch.float64)
             R = ref[n]
             ke = float(0.5 * (r * (ux * ux + uy * uy)).sum())
             umax = max(float(R["ux"].abs().max()), float(R["uy"].abs().max()))
@@ -373,15 +436,16 @@ def bench_precision(inp, checkpoints=(100, 1000, 5000)):
             nk = min(len(spec), len(R["spec"]))
             rel = (spec[:nk] - R["spec"][:nk]).abs() / R["spec"][:nk]
             res[str(n)] = {
-                "eps_f": float((f.double() - R["f"].double()).abs().max() / R["f"].double().abs().max()),
-                "eps_u_inf": max(float((ux.cpu() - R["ux"]).abs().max()), float((uy.cpu() - R["uy"]).abs().max())) / umax,
-                "eps_u_l2": float(torch.sqrt(((ux.cpu() - R["ux"]) ** 2 + (uy.cpu() - R["uy"]) ** 2).sum()
+                "eps_f": float((f - R["f"]).abs().max() / R["f"].abs().max()),
+                "eps_u_inf": max(float((ux - R["ux"]).abs().max()), float((uy - R["uy"]).abs().max())) / umax,
+                "eps_u_l2": float(torch.sqrt(((ux - R["ux"]) ** 2 + (uy - R["uy"]) ** 2).sum()
                                              / (R["ux"] ** 2 + R["uy"] ** 2).sum())),
-                "eps_rho": float((r.cpu() - R["rho"]).abs().max() / (R["rho"] - w.rho0).abs().max()),
+                "eps_rho": float((r - R["rho"]).abs().max() / (R["rho"] - w.rho0).abs().max()),
                 "ke_rel": ke / R["ke"] - 1.0,
                 "spectrum_max_rel_K4_64": float(rel[4:65].max()),
                 "spectrum_rel_l1": float((spec[:nk] - R["spec"][:nk]).abs().sum() / R["spec"][:nk].sum()),
             }
+            del f
         out[storage] = res
         del s
     return out
@@ -455,45 +519,52 @@ def bench_shocktube(cases=((0.4, 1e-12), (0.55, 1e-9)), models=("bgk", "uc", "pa
             "runs": runs, "seconds": time.perf_counter() - t0}
 
 
+def _time_adjoint(sim, z, spin_s=0.2, reps=3):
+    """Milliseconds of one sim.adjoint call in the steady state (calls for about spin_s seconds
+    first, then `reps` timed calls without a pause)."""
+    import torch
+    t0 = time.perf_counter()
+    while time.perf_counter() - t0 < spin_s:
+        sim.adjoint(None, z + 1e-3, z)
+        torch.cuda.synchronize()
+    sim.adjoint(None, z + 1e-3, z)
+    s, e = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    s.record(sim.stream)
+    for _ in range(reps):
+        sim.adjoint(None, z + 1e-3, z)
+    e.record(sim.stream)
+    torch.cuda.synchronize()
+    return s.elapsed_time(e) / reps
+
+
 def bench_adjoint(inp):
     import torch
     res = {}
-    # Adjoint step kernel alone: time the reverse sweep of a recorded run and subtract the
-    # recomputation (a forward step with moment recording per adjoint step).
+    # Reverse sweep of a recorded 64-step run at 4096^2: recomputation from each checkpoint
+    # (spacing 8) with moment recording, then the adjoint steps.
     w = inp.WORKLOADS["tg4096"]
     fields = w.fields(seed=0)
     N = 64
+    nodes = w.nx * w.ny
+    z = torch.zeros((w.ny, w.nx), dtype=torch.float32, device="cuda")
     sim = make_sim(w, "complete", "f32", "ab", fields, record_steps=N, ckpt_stride=8)
     sim.step(N)
-    z = torch.zeros((w.ny, w.nx), dtype=torch.float32, device="cuda")
-    sim.adjoint(None, z + 1e-3, z)  # warm-up
-    torch.cuda.synchronize()
-    s, e = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    s.record(sim.stream)
-    sim.adjoint(None, z + 1e-3, z)
-    e.record(sim.stream)
-    torch.cuda.synchronize()
-    ms_sweep = s.elapsed_time(e)
-    nodes = w.nx * w.ny
+    ms_sweep = _time_adjoint(sim, z)
     res["adjoint/tg4096/complete/f32/sweep"] = {
         "steps": N, "ms_total": ms_sweep, "GLUPS_gradient_sweep": nodes * N / (ms_sweep * 1e-3) / 1e9,
         "note": "reverse sweep = recorded recomputation from each checkpoint + adjoint step per step"}
     del sim
     # The same sweep with one checkpoint segment: the forward run kept the moments of every
-    # step (64 x 20 B per node), so the sweep is the adjoint kernels alone.
+    # step (64 x 20 B per node), so the sweep is the adjoint kernels alone (92 B per node and
+    # reverse step: fbar read and written, five recorded moments read).
     sim = make_sim(w, "complete", "f32", "ab", fields, record_steps=N, ckpt_stride=N)
     sim.step(N)
-    sim.adjoint(None, z + 1e-3, z)  # warm-up
-    torch.cuda.synchronize()
-    s.record(sim.stream)
-    sim.adjoint(None, z + 1e-3, z)
-    e.record(sim.stream)
-    torch.cuda.synchronize()
-    ms_one = s.elapsed_time(e)
+    ms_one = _time_adjoint(sim, z)
     res["adjoint/tg4096/complete/f32/sweep_one_segment"] = {
         "steps": N, "ms_total": ms_one, "GLUPS_gradient_sweep": nodes * N / (ms_one * 1e-3) / 1e9,
+        "hbm_frac_at_92B_per_update": 92 * nodes * N / (ms_one * 1e-3) / 1e9 / HBM_PEAK_GBS,
         "note": "ckpt_stride = N: moments of every step kept from the forward run, no recomputation"}
-    del sim
+    del sim, z
     # End-to-end gradient of the final kinetic energy on the 1024^2 shear wave.
     from paper_2602_21242_amd import LBMFunction
     wa = inp.WORKLOADS["shear1024"]
@@ -501,34 +572,73 @@ def bench_adjoint(inp):
     cfg = dict(nx=wa.nx, ny=wa.ny, theta=wa.theta, nu=wa.nu, steps=wa.steps, model="complete", storage="f32",
                pattern="ab")
     t = lambda a: torch.as_tensor(a, dtype=torch.float32, device="cuda")
-    for rep in range(2):
-        ux0 = t(ux).requires_grad_(True)
-        uy0 = t(uy).requires_grad_(True)
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        r, vx, vy = LBMFunction.apply(ux0, uy0, cfg)
-        E = 0.5 * (r * (vx * vx + vy * vy)).sum()
-        E.backward()
-        torch.cuda.synchronize()
-        dt = time.perf_counter() - t0
-    res["gradient/shear1024/complete/f32/ab"] = {
-        "steps": wa.steps, "s_total": dt, "GLUPS_end_to_end": wa.nx * wa.ny * wa.steps / dt / 1e9,
-        "note": "forward with checkpoints + recomputation + adjoint, cache-resident size"}
-    cfg1 = dict(cfg, ckpt_stride=wa.steps)
-    for rep in range(2):
-        ux0 = t(ux).requires_grad_(True)
-        uy0 = t(uy).requires_grad_(True)
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        r, vx, vy = LBMFunction.apply(ux0, uy0, cfg1)
-        E = 0.5 * (r * (vx * vx + vy * vy)).sum()
-        E.backward()
-        torch.cuda.synchronize()
-        dt1 = time.perf_counter() - t0
-    res["gradient/shear1024/complete/f32/ab/one_segment"] = {
-        "steps": wa.steps, "s_total": dt1, "GLUPS_end_to_end": wa.nx * wa.ny * wa.steps / dt1 / 1e9,
-        "note": "ckpt_stride = steps: forward keeps every step's moments (10.5 GB), sweep without recomputation"}
+    for key, c, note in (("gradient/shear1024/complete/f32/ab", cfg,
+                          "forward with checkpoints + recomputation + adjoint, cache-resident size"),
+                         ("gradient/shear1024/complete/f32/ab/one_segment", dict(cfg, ckpt_stride=wa.steps),
+                          "ckpt_stride = steps: forward keeps every step's moments (10.5 GB), sweep without "
+                          "recomputation")):
+        for rep in range(3):
+            ux0 = t(ux).requires_grad_(True)
+            uy0 = t(uy).requires_grad_(True)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            r, vx, vy = LBMFunction.apply(ux0, uy0, c)
+            E = 0.5 * (r * (vx * vx + vy * vy)).sum()
+            E.backward()
+            torch.cuda.synchronize()
+            dt = time.perf_counter() - t0
+        res[key] = {"steps": wa.steps, "s_total": dt, "GLUPS_end_to_end": wa.nx * wa.ny * wa.steps / dt / 1e9,
+                    "note": note}
     return res
+
+
+def _enstrophy(ux, uy):
+    """Half the sum of the squared central-difference vorticity (periodic), in FP64."""
+    import torch
+    wz = 0.5 * (torch.roll(uy, -1, 1) - torch.roll(uy, 1, 1)) - 0.5 * (torch.roll(ux, -1, 0) - torch.roll(ux, 1, 0))
+    return 0.5 * (wz.double() * wz.double()).sum()
+
+
+def bench_gradient_dsl(inp):
+    """End-to-end gradient on the 16384 x 4096 double shear layer: the 3000-step FP32 forward
+    with sqrt(N) checkpoints (55-step spacing), the final enstrophy, and its gradient with
+    respect to the initial velocity (recomputation of every checkpoint segment but the last,
+    and the adjoint sweep); about 219 GB of workspace. Skipped when the device lacks the
+    memory."""
+    import torch
+    from paper_2602_21242_amd import LBMFunction, capi
+    w = inp.WORKLOADS["dsl16384"]
+    p = capi.make_params(w.nx, w.ny, w.theta, w.nu, model="complete", storage="f32", pattern="ab",
+                         record_steps=w.steps)
+    need = capi.lbm_workspace_bytes(p)[1]
+    free = torch.cuda.mem_get_info()[0]
+    key = f"gradient/dsl16384/complete/f32/ab"
+    if free < need + (8 << 30):
+        return {key: {"skipped": f"needs {need / 1e9:.0f} GB of device memory, {free / 1e9:.0f} GB free"}}
+    rho, ux, uy = w.fields(seed=0)
+    cfg = dict(nx=w.nx, ny=w.ny, theta=w.theta, nu=w.nu, steps=w.steps, model="complete", storage="f32",
+               pattern="ab")
+    ux0 = torch.as_tensor(ux, dtype=torch.float32, device="cuda").requires_grad_(True)
+    uy0 = torch.as_tensor(uy, dtype=torch.float32, device="cuda").requires_grad_(True)
+    del rho, ux, uy
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    r, vx, vy = LBMFunction.apply(ux0, uy0, cfg)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    _enstrophy(vx, vy).backward()
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    nodes = w.nx * w.ny
+    out = {key: {"steps": w.steps, "workspace_GB": need / 1e9, "s_forward": t1 - t0, "s_backward": t2 - t1,
+                 "GLUPS_end_to_end": nodes * w.steps / (t2 - t0) / 1e9,
+                 "GLUPS_forward_recorded": nodes * w.steps / (t1 - t0) / 1e9,
+                 "grad_uy0_l2": float(uy0.grad.double().norm()),
+                 "note": "forward with 55-step checkpoints (first launches include the context set-up), "
+                         "enstrophy, recomputation + adjoint sweep + initial-condition adjoint"}}
+    del r, vx, vy, ux0, uy0
+    torch.cuda.empty_cache()
+    return out
 
 
 if __name__ == "__main__":

@@ -70,7 +70,11 @@ typedef enum { LBM_F64 = 0, LBM_F32 = 1, LBM_BF16 = 2, LBM_F16 = 3 } lbm_dtype;
 typedef enum { LBM_AB = 0, LBM_AA = 1 } lbm_pattern;
 
 typedef struct {
-  int32_t nx, ny;        /* periodic box, 1 <= nx, ny; (nx+63)/64*64*ny < 2^31 */
+  int32_t nx, ny;        /* periodic box, 1 <= nx, ny; with pitch = (nx+63)/64*64 (rows of whole
+                            64-node groups): pitch*ny < 2^31, and 9*pitch*E < 2^31 bytes, E the
+                            larger of the storage and compute element sizes (8 for LBM_F64, else
+                            4), because the kernels address a lattice row with 32-bit byte
+                            offsets; wider rows give LBM_ERR_INVALID_ARGUMENT */
   double theta;          /* reduced lattice temperature, 0 < theta < 1 */
   double nu;             /* lattice viscosity > 0; tau = nu/theta + 1/2 (nu = theta (tau - 1/2)) */
   double rho0;           /* reference density > 0 (storage shift) */
@@ -124,7 +128,8 @@ lbm_status lbm_init(const lbm_params* p, void* d_workspace, size_t workspace_byt
  * allowed but disables lbm_adjoint. */
 lbm_status lbm_step(lbm_ctx* ctx, int64_t n);
 
-/* Density and velocity rho = sum_i f_i, u = sum_i c_i f_i / rho of the pre-collision
+/* Density and velocity rho = sum_i f_i, u = sum_i c_i f_i / rho (the macroscopic densities the
+ * paper defines from the populations right after eq:lbe, Sec. 1) of the pre-collision
  * state f^n at the current time n, written to FP64 or FP32 [ny][nx] arrays
  * (out_dtype LBM_F64 or LBM_F32; the 16-bit types give LBM_ERR_UNSUPPORTED). Any output
  * pointer may be NULL. */
@@ -138,10 +143,14 @@ lbm_status lbm_get_populations(lbm_ctx* ctx, lbm_dtype out_dtype, void* d_f);
  * NULL; rounded to the storage type). Disables lbm_adjoint for the recorded run. */
 lbm_status lbm_set_populations(lbm_ctx* ctx, const double* d_f);
 
-/* FP64 totals of the pre-collision state: out[0] = sum rho, out[1] = sum rho u_x,
- * out[2] = sum rho u_y (the only FP64 arithmetic of the reduced-precision paths).
- * Waits for the stream. Returns LBM_ERR_NONFINITE (with out filled) if any population
- * is NaN or infinite. */
+/* FP64 totals of the pre-collision state: out[0] = sum_x rho, out[1] = sum_x rho u_x,
+ * out[2] = sum_x rho u_y, with rho and rho u the population moments of Sec. 1. They are the
+ * quantities every collision model keeps (eq:density-momentum: the equilibrium carries the
+ * node's rho and rho u; eq:genOReg-constraints: the corrected non-equilibrium populations
+ * carry no mass and no momentum), so streaming and collision conserve them, except the
+ * uncorrected OReg model's momentum. Computed on the device in FP64, the only FP64
+ * reduction of the reduced-precision paths. Waits for the stream. Returns
+ * LBM_ERR_NONFINITE (with out filled) if any population is NaN or infinite. */
 lbm_status lbm_invariants(lbm_ctx* ctx, double out[3]);
 
 /* Discrete adjoint of the recorded run (requires record_steps = N > 0 and lbm_time = N).

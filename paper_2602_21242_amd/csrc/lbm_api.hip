@@ -34,6 +34,7 @@ lbm_status fail(lbm_status s, const std::string& msg) {
 size_t round_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
 
 size_t storage_size(int dt) { return dt == LBM_F64 ? 8 : dt == LBM_F32 ? 4 : 2; }
+size_t compute_size(int dt) { return dt == LBM_F64 ? 8 : 4; }
 
 // Workspace regions (byte offsets into the caller's buffer).
 struct Plan {
@@ -52,16 +53,26 @@ struct Plan {
 // Elements per population row: nx rounded up to whole 64-node groups (lane-strided rows).
 int64_t row_pitch(int64_t nx) { return (nx + 63) / 64 * 64; }
 
+// Largest byte offset within one lattice row (its nine population rows, in the storage type
+// or, for the adjoint's buffers, the compute type) that the kernels address: they add 32-bit
+// in-row byte offsets to a row's base.
+constexpr int64_t kMaxRowBytes = int64_t(1) << 31;
+
 lbm_status validate(const lbm_params* p) {
   if (!p) return fail(LBM_ERR_INVALID_ARGUMENT, "params is NULL");
   if (p->nx < 1 || p->ny < 1) return fail(LBM_ERR_INVALID_ARGUMENT, "nx and ny must be >= 1");
+  if (p->storage < LBM_F64 || p->storage > LBM_F16) return fail(LBM_ERR_INVALID_ARGUMENT, "unknown storage type");
   if (row_pitch(p->nx) * int64_t(p->ny) >= (int64_t(1) << 31))
     return fail(LBM_ERR_INVALID_ARGUMENT, "grid too large: (nx rounded up to 64) * ny must be < 2^31");
+  const int64_t elem = int64_t(std::max(storage_size(p->storage), compute_size(p->storage)));
+  if (int64_t(lbm::Q) * row_pitch(p->nx) * elem >= kMaxRowBytes)
+    return fail(LBM_ERR_INVALID_ARGUMENT,
+                "grid too wide: 9 * (nx rounded up to 64) * (larger of the storage and compute element sizes) "
+                "must be < 2^31 bytes");
   if (!(p->theta > 0.0 && p->theta < 1.0)) return fail(LBM_ERR_INVALID_ARGUMENT, "theta must lie in (0, 1)");
   if (!(p->nu > 0.0) || !std::isfinite(p->nu)) return fail(LBM_ERR_INVALID_ARGUMENT, "nu must be finite and > 0");
   if (!(p->rho0 > 0.0) || !std::isfinite(p->rho0)) return fail(LBM_ERR_INVALID_ARGUMENT, "rho0 must be finite and > 0");
   if (p->model < LBM_BGK || p->model > LBM_OREG_COMPLETE) return fail(LBM_ERR_INVALID_ARGUMENT, "unknown model");
-  if (p->storage < LBM_F64 || p->storage > LBM_F16) return fail(LBM_ERR_INVALID_ARGUMENT, "unknown storage type");
   if (p->pattern != LBM_AB && p->pattern != LBM_AA) return fail(LBM_ERR_INVALID_ARGUMENT, "unknown pattern");
   if (p->record_steps < 0) return fail(LBM_ERR_INVALID_ARGUMENT, "record_steps must be >= 0");
   if (p->ckpt_stride < 0) return fail(LBM_ERR_INVALID_ARGUMENT, "ckpt_stride must be >= 0");
@@ -78,7 +89,7 @@ lbm_status validate(const lbm_params* p) {
 Plan make_plan(const lbm_params& p) {
   Plan pl;
   pl.esize = storage_size(p.storage);
-  pl.tsize = p.storage == LBM_F64 ? 8 : 4;
+  pl.tsize = compute_size(p.storage);
   const size_t pitch = size_t(row_pitch(p.nx));
   // Row-interleaved buffers: ny rows of nine (populations) or five (recorded moments)
   // population rows of `pitch` elements each, rounded up to 4 KiB.

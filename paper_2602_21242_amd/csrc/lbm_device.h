@@ -37,11 +37,8 @@ __device__ __forceinline__ T sel(int c, T m, T z, T p) { return c < 0 ? m : (c >
 // ---------------------------------------------------------------------------------------
 // Storage element types and conversions (round to nearest even into 16-bit types).
 template <class S> struct StorageTraits;
-// kShortCollide: the storage type's step kernels use collide's shorter final assembly
-// (chosen where the kernels are limited by vector arithmetic; see collide).
 template <> struct StorageTraits<double> {
   using T = double;
-  static constexpr bool kShortCollide = false;
   using Raw = double;
   static __device__ __forceinline__ double load(double v) { return v; }
   static __device__ __forceinline__ double load_raw(double v) { return v; }
@@ -49,7 +46,6 @@ template <> struct StorageTraits<double> {
 };
 template <> struct StorageTraits<float> {
   using T = float;
-  static constexpr bool kShortCollide = false;
   using Raw = float;
   static __device__ __forceinline__ float load(float v) { return v; }
   static __device__ __forceinline__ float load_raw(float v) { return v; }
@@ -57,7 +53,6 @@ template <> struct StorageTraits<float> {
 };
 template <> struct StorageTraits<_Float16> {
   using T = float;
-  static constexpr bool kShortCollide = true;
   // Loaded populations wait for their use as zero-extended 32-bit bit patterns. Kept as
   // _Float16 values, the compiler packs pairs of them into one register right after the
   // loads, which stalls on the loads there instead of at their first use (the two-step
@@ -74,7 +69,6 @@ template <> struct StorageTraits<_Float16> {
 struct bf16_t { uint16_t bits; };
 template <> struct StorageTraits<bf16_t> {
   using T = float;
-  static constexpr bool kShortCollide = true;
   using Raw = bf16_t;
   static __device__ __forceinline__ float load(bf16_t v) { return __uint_as_float(uint32_t(v.bits) << 16); }
   static __device__ __forceinline__ float load_raw(bf16_t v) { return load(v); }
@@ -120,19 +114,17 @@ __device__ __forceinline__ float recip<float>(float x) {
 // Collision of one node on shifted populations: g -> g* (eq:lbe, first line, with the
 // non-equilibrium part of the chosen model). Optionally returns the recorded moments.
 //
-// The arithmetic is arranged for few vector instructions (the 16-bit storage paths are
-// ALU-bound): the moments come from pair sums; the equilibrium and f^OReg share the
-// product Phi_x Phi_y, g*_i = P_i (drho + t_i) + E_i + Psi_i; and the moments of f^OReg that
-// the corrections need (psi and the prefactor's sum) use their closed forms in N_xx and u,
-// which follow from the per-axis moments of Phi: sum Phi = 1, sum c Phi = u,
-// sum c^2 Phi = theta + u^2, and c^3 = c, c^4 = c^2 on {-1, 0, 1}.
-// SHORT selects a regrouping of the final assembly, g*_i = Phi_y (K_x + Phi_x v_i) + c_i with
-// K_x = Phi_x (drho + ...) + rho0 d_x per value of c_x: three FMAs per population instead of
-// about six (10 % fewer vector instructions). The 16-bit storage paths, which are limited by
-// vector arithmetic, use it; the FP32/FP64 kernels are not, and keep the P_i, E_i form
-// (measured on MI355X, 8192^2: BF16 complete +2 %, LBGK two-step FP16 +4 % and BF16 +5 %,
-// FP16 complete unchanged; the FP32 two-step kernel lost 6 % with it).
-template <class T, int MODEL, bool SHORT = false>
+// The arithmetic is arranged for few vector instructions: the moments come from pair sums;
+// the equilibrium and f^OReg share the per-axis factors Phi_x Phi_y; and the moments of f^OReg
+// that the corrections need (psi and the prefactor's sum) use their closed forms in N_xx and
+// u, which follow from the per-axis moments of Phi: sum Phi = 1, sum c Phi = u,
+// sum c^2 Phi = theta + u^2, and c^3 = c, c^4 = c^2 on {-1, 0, 1}. The final assembly is
+// g*_i = Phi_y (K_x + Phi_x v_i) + c_i with K_x = Phi_x (drho + ...) + rho0 d_x formed once per
+// value of c_x: three FMAs per population. (The longer form P_i (drho + t_i) + E_i + Psi_i,
+// P_i = Phi_x Phi_y, needs about six; with the two-step kernel's buffer accesses the short form
+// measured faster for every storage type on MI355X: FP32 pair 150.1 -> 153.6 GLUPS at 4096^2,
+// 152.2 -> 156.8 at 8192^2, FP64 pair 77.3 -> 78.5.)
+template <class T, int MODEL>
 __device__ __forceinline__ void collide(const T g[Q], T out[Q], const Coef<T>& k, T rec[NREC]) {
   // Moments (Sec. 1): rho = rho0 + sum g, j = sum c g, D = sum (cx^2 - cy^2) g, Pxy = sum cx cy g.
   const T s13 = g[1] + g[3], s24 = g[2] + g[4], s57 = g[5] + g[7], s68 = g[6] + g[8];
@@ -157,16 +149,6 @@ __device__ __forceinline__ void collide(const T g[Q], T out[Q], const Coef<T>& k
   const T rdx0 = k.rho0 * dx0, rdxp = k.rho0 * dxp, rdxm = k.rho0 * dxm;
   const T a0m = k.rr0 * dym, a00 = k.rr0 * dy0, a0p = k.rr0 * dyp;  // rho0 r_x d_y, c_x = 0
   const T a1m = k.rr1 * dym, a10 = k.rr1 * dy0, a1p = k.rr1 * dyp;  // rho0 r_x d_y, c_x = +-1
-  T P[Q], E[Q];
-  if constexpr (!SHORT) {
-#pragma unroll
-    for (int i = 0; i < Q; ++i) {
-      const T hx = sel(cx(i), hxm, hx0, hxp), hy = sel(cy(i), hym, hy0, hyp);
-      const T rdy = cx(i) == 0 ? sel(cy(i), a0m, a00, a0p) : sel(cy(i), a1m, a10, a1p);
-      P[i] = hx * hy;
-      E[i] = sel(cx(i), rdxm, rdx0, rdxp) * hy + rdy;
-    }
-  }
   if (rec) {
     rec[0] = rho;
     rec[1] = ux;
@@ -174,18 +156,13 @@ __device__ __forceinline__ void collide(const T g[Q], T out[Q], const Coef<T>& k
   }
 
   if (MODEL == M_BGK) {
-    // SHORT: feqs_i = Phi_y (Phi_x drho + rho0 d_x) + rho0 r_x d_y
+    // f_i^eq - w_i rho0 = Phi_y (Phi_x drho + rho0 d_x) + rho0 r_x d_y
     const T Km = hxm * drho + rdxm, K0 = hx0 * drho + rdx0, Kp = hxp * drho + rdxp;
 #pragma unroll
     for (int i = 0; i < Q; ++i) {
-      T feqs;
-      if constexpr (SHORT) {
-        const T hy = sel(cy(i), hym, hy0, hyp);
-        const T rdy = cx(i) == 0 ? sel(cy(i), a0m, a00, a0p) : sel(cy(i), a1m, a10, a1p);
-        feqs = hy * sel(cx(i), Km, K0, Kp) + rdy;
-      } else {
-        feqs = drho * P[i] + E[i];
-      }
+      const T hy = sel(cy(i), hym, hy0, hyp);
+      const T rdy = cx(i) == 0 ? sel(cy(i), a0m, a00, a0p) : sel(cy(i), a1m, a10, a1p);
+      const T feqs = hy * sel(cx(i), Km, K0, Kp) + rdy;
       out[i] = feqs + k.omb * (g[i] - feqs);
     }
     if (rec) rec[3] = rec[4] = T(0);
@@ -247,25 +224,16 @@ __device__ __forceinline__ void collide(const T g[Q], T out[Q], const Coef<T>& k
       Psi[6] = Psi[8] = s + T(0.5) * hPtxy;
     }
   }
-  // g*_i = (f_i^eq - w_i rho0) + (1 - 1/tau)(f_i^OReg + Psi_i) = P_i (drho + t_i) + E_i + Psi_i
-  // SHORT: = Phi_y (K_x + Phi_x (C_x Y2 - Y1)) + (rho0 r_x d_y + Psi_i), with
+  // g*_i = (f_i^eq - w_i rho0) + (1 - 1/tau)(f_i^OReg + Psi_i)
+  //      = Phi_y (K_x + Phi_x (C_x Y2 - Y1)) + (rho0 r_x d_y + Psi_i), with
   // drho + t_i = X1 - Y1 + C_x Y2 and K_x = Phi_x X1 + rho0 d_x per value of c_x.
-  if constexpr (SHORT) {
-    const T Km = hxm * X1m + rdxm, K0 = hx0 * X10 + rdx0, Kp = hxp * X1p + rdxp;
+  const T Km = hxm * X1m + rdxm, K0 = hx0 * X10 + rdx0, Kp = hxp * X1p + rdxp;
 #pragma unroll
-    for (int i = 0; i < Q; ++i) {
-      const T hx = sel(cx(i), hxm, hx0, hxp), hy = sel(cy(i), hym, hy0, hyp);
-      const T rdy = cx(i) == 0 ? sel(cy(i), a0m, a00, a0p) : sel(cy(i), a1m, a10, a1p);
-      const T v = sel(cx(i), Cxm, Cx0, Cxp) * sel(cy(i), Y2m, Y20, Y2p) - sel(cy(i), Y1m, Y10, Y1p);
-      out[i] = hy * (sel(cx(i), Km, K0, Kp) + hx * v) + (rdy + Psi[i]);
-    }
-  } else {
-#pragma unroll
-    for (int i = 0; i < Q; ++i) {
-      const T u = sel(cx(i), X1m, X10, X1p) - sel(cy(i), Y1m, Y10, Y1p) +
-                  sel(cx(i), Cxm, Cx0, Cxp) * sel(cy(i), Y2m, Y20, Y2p);
-      out[i] = P[i] * u + (E[i] + Psi[i]);
-    }
+  for (int i = 0; i < Q; ++i) {
+    const T hx = sel(cx(i), hxm, hx0, hxp), hy = sel(cy(i), hym, hy0, hyp);
+    const T rdy = cx(i) == 0 ? sel(cy(i), a0m, a00, a0p) : sel(cy(i), a1m, a10, a1p);
+    const T v = sel(cx(i), Cxm, Cx0, Cxp) * sel(cy(i), Y2m, Y20, Y2p) - sel(cy(i), Y1m, Y10, Y1p);
+    out[i] = hy * (sel(cx(i), Km, K0, Kp) + hx * v) + (rdy + Psi[i]);
   }
 }
 

@@ -112,6 +112,62 @@ __device__ __forceinline__ S* at(char* base, int p) {
   return reinterpret_cast<S*>(base + uint32_t(p) * uint32_t(sizeof(S)));
 }
 
+// Buffer-resource accesses of the two-step forward kernel. One lattice row of a
+// buffer (its nine population rows, or the five rows of a moment record) is described by a
+// buffer resource in scalar registers, rebased to that row; an access adds the scalar offset
+// of the population (or record entry) within the lattice row and the lane's 32-bit in-row
+// byte offset, which stays in one vector register for the whole loop. (With plain pointers
+// the compiler folded the loop-invariant lane offsets into nine 64-bit per-population
+// addresses and added each row's offset to them in 64-bit vector arithmetic: 39 of the 333
+// vector instructions of the FP32 two-step kernel's row loop; with buffer accesses and the
+// scheduling fence of pair_sync the FP32 pair went from 142.6 to 150.1 GLUPS at 4096^2, FP16
+// and BF16 from 183 to 189-190 at 8192^2.) The adjoint kernels keep plain pointers: the
+// two-step adjoint ran 5 % slower with buffer accesses (433 against 414 us per launch at
+// 4096^2), whatever its occupancy. Offsets within a lattice row stay below 2^31 bytes:
+// lbm_init rejects wider rows.
+constexpr int kRsrcWord3 = 0x00020000;  // resource word 3 of a raw buffer on the gfx9 family
+constexpr int kAuxNT = 2;                // cache-policy operand of a nontemporal access (gfx950)
+
+struct RowRes {
+  __amdgpu_buffer_rsrc_t r;
+};
+
+// Lattice row y of a buffer whose lattice rows are row_bytes apart.
+__device__ __forceinline__ RowRes row_res(const void* buf, size_t row_bytes, int y) {
+  char* base = const_cast<char*>(static_cast<const char*>(buf)) + size_t(y) * row_bytes;
+  return RowRes{__builtin_amdgcn_make_buffer_rsrc(base, 0, int(uint32_t(row_bytes)), kRsrcWord3)};
+}
+
+// Element (soff + voff bytes into the lattice row) in the register form
+// StorageTraits<E>::Raw for storage types, or as E itself for the compute types.
+template <class E, bool NT>
+__device__ __forceinline__ auto ldb(const RowRes& rr, int soff, uint32_t voff) {
+  constexpr int aux = NT ? kAuxNT : 0;
+  if constexpr (sizeof(E) == 8) {
+    return __builtin_bit_cast(E, __builtin_amdgcn_raw_buffer_load_b64(rr.r, int(voff), soff, aux));
+  } else if constexpr (sizeof(E) == 4) {
+    return __builtin_bit_cast(E, __builtin_amdgcn_raw_buffer_load_b32(rr.r, int(voff), soff, aux));
+  } else {
+    const uint16_t h = __builtin_amdgcn_raw_buffer_load_b16(rr.r, int(voff), soff, aux);
+    using R = typename StorageTraits<E>::Raw;
+    if constexpr (std::is_same_v<R, uint32_t>) return uint32_t(h);
+    else return __builtin_bit_cast(E, h);
+  }
+}
+
+// Nontemporal store of one element (every kernel writes each location once per launch).
+template <class E>
+__device__ __forceinline__ void stb(const RowRes& rr, int soff, uint32_t voff, E v) {
+  if constexpr (sizeof(E) == 8) {
+    using V2 = unsigned int __attribute__((ext_vector_type(2)));
+    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(V2, v), rr.r, int(voff), soff, kAuxNT);
+  } else if constexpr (sizeof(E) == 4) {
+    __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(uint32_t, v), rr.r, int(voff), soff, kAuxNT);
+  } else {
+    __builtin_amdgcn_raw_buffer_store_b16(__builtin_bit_cast(uint16_t, v), rr.r, int(voff), soff, kAuxNT);
+  }
+}
+
 // In-row positions of a node and of its periodic x-neighbours.
 struct RowPos {
   int p0, pm, pp;  // pos(x), pos(x - 1), pos(x + 1)
@@ -192,7 +248,7 @@ k_step(const S* src, S* dst, Geo geo, Coef<typename StorageTraits<S>::T> k,
     T g[Q], out[Q], rv[NREC];
 #pragma unroll
     for (int i = 0; i < Q; ++i) g[i] = Tr::load_raw(gs[n][i]);
-    collide<T, MODEL, Tr::kShortCollide>(g, out, k, REC ? rv : nullptr);
+    collide<T, MODEL>(g, out, k, REC ? rv : nullptr);
     if constexpr (REC) {
       char* rrow = reinterpret_cast<char*>(rec) + y * (size_t(rec_rs) * sizeof(T));
 #pragma unroll
@@ -247,6 +303,16 @@ __device__ __forceinline__ void xcd_tile(int& bx, int& by) {
   by = t / nx;
 }
 
+// Block barrier of the two-step kernels, which is also a scheduling fence: no instruction
+// moves across it. Without the fence the scheduler hoisted phase A's collision (it reads only
+// the registers the previous row's loads fill) above the preceding barrier and phase B, so
+// each row waited for its loads before phase B instead of after it: the FP32 pair lost 5 %
+// (LBGK 11 %) once its addresses no longer tied the loads to their place in the loop.
+__device__ __forceinline__ void pair_sync() {
+  __syncthreads();
+  __builtin_amdgcn_sched_barrier(0);
+}
+
 // Whether the two-step kernel's interior wavefronts load with the nontemporal hint. Without
 // it, the groups a block re-reads as halo stay in L2 for the neighbouring block that reads
 // them too. Measured on MI355X, complete model, HBM bytes read per node and launch with /
@@ -263,12 +329,12 @@ __device__ __forceinline__ void load_pulled(const S* src, const Geo& geo, int r,
   const int y = r < 0 ? r + geo.ny : (r >= geo.ny ? r - geo.ny : r);
   const int ym = (y == 0) ? geo.ny - 1 : y - 1;
   const int yp = (y == geo.ny - 1) ? 0 : y + 1;
-  const size_t rsb = size_t(geo.rs) * sizeof(S), psb = size_t(geo.ps) * sizeof(S);
-  const char* sr[3] = {reinterpret_cast<const char*>(src) + ym * rsb, reinterpret_cast<const char*>(src) + y * rsb,
-                       reinterpret_cast<const char*>(src) + yp * rsb};
+  const size_t rsb = size_t(geo.rs) * sizeof(S);
+  const int psb = geo.ps * int(sizeof(S));
+  const RowRes sr[3] = {row_res(src, rsb, ym), row_res(src, rsb, y), row_res(src, rsb, yp)};
   static_for<0, Q>([&](auto I) {
     constexpr int i = decltype(I)::value;
-    gs[i] = ld_raw<S, NT>(at<S>(sr[-cy(i) + 1] + i * psb, rp.template of<-cx(i)>()));
+    gs[i] = ldb<S, NT>(sr[-cy(i) + 1], i * psb, uint32_t(rp.template of<-cx(i)>()) * uint32_t(sizeof(S)));
   });
 }
 
@@ -310,7 +376,8 @@ k_step2(const S* __restrict__ src, S* __restrict__ dst, Geo geo, Coef<typename S
   }
   const bool interior = w >= 1 && w <= G;
   const int pb = (s0 + w - 1) * kLanes + lane;  // phase-B output position
-  const size_t rsb = size_t(geo.rs) * sizeof(S), psb = size_t(geo.ps) * sizeof(S);
+  const size_t rsb = size_t(geo.rs) * sizeof(S);
+  const int psb = geo.ps * int(sizeof(S));
 
   typename Tr::Raw gs[Q];
   // Phase A of row r: step 1 of the wavefront's node from gs into the ring slot of row r
@@ -320,14 +387,14 @@ k_step2(const S* __restrict__ src, S* __restrict__ dst, Geo geo, Coef<typename S
     T g[Q], out[Q], rv[NREC];
 #pragma unroll
     for (int i = 0; i < Q; ++i) g[i] = Tr::load_raw(gs[i]);
-    collide<T, MODEL, Tr::kShortCollide>(g, out, k, REC ? rv : nullptr);
+    collide<T, MODEL>(g, out, k, REC ? rv : nullptr);
 #pragma unroll
     for (int i = 0; i < Q; ++i) ring[slot][w][i][lane] = Tr::store(out[i]);
     if constexpr (REC) {
       if (interior && r >= y0 && r < y1) {
-        char* rrow = reinterpret_cast<char*>(rec1) + r * (size_t(rec_rs) * sizeof(T));
+        const RowRes rr = row_res(rec1, size_t(rec_rs) * sizeof(T), r);
 #pragma unroll
-        for (int j = 0; j < NREC; ++j) st1(at<T>(rrow + j * size_t(geo.ps) * sizeof(T), pb), rv[j]);
+        for (int j = 0; j < NREC; ++j) stb<T>(rr, j * geo.ps * int(sizeof(T)), pb * uint32_t(sizeof(T)), rv[j]);
       }
     }
   };
@@ -339,15 +406,15 @@ k_step2(const S* __restrict__ src, S* __restrict__ dst, Geo geo, Coef<typename S
       g[i] = Tr::load(ring[(yr - cy(i) - y0 + 1) % 3][w - cx(i)][i][lane]);
     });
     T rv[NREC];
-    collide<T, MODEL, Tr::kShortCollide>(g, out, k, REC ? rv : nullptr);
+    collide<T, MODEL>(g, out, k, REC ? rv : nullptr);
     if constexpr (REC) {
-      char* rrow = reinterpret_cast<char*>(rec2) + yr * (size_t(rec_rs) * sizeof(T));
+      const RowRes rr = row_res(rec2, size_t(rec_rs) * sizeof(T), yr);
 #pragma unroll
-      for (int j = 0; j < NREC; ++j) st1(at<T>(rrow + j * size_t(geo.ps) * sizeof(T), pb), rv[j]);
+      for (int j = 0; j < NREC; ++j) stb<T>(rr, j * geo.ps * int(sizeof(T)), pb * uint32_t(sizeof(T)), rv[j]);
     }
-    char* drow = reinterpret_cast<char*>(dst) + yr * rsb;
+    const RowRes dr = row_res(dst, rsb, yr);
 #pragma unroll
-    for (int i = 0; i < Q; ++i) st1(at<S>(drow + i * psb, pb), Tr::store(out[i]));
+    for (int i = 0; i < Q; ++i) stb<S>(dr, i * psb, pb * uint32_t(sizeof(S)), Tr::store(out[i]));
   };
   auto load = [&](const int r) { load_pulled<S>(src, geo, r, ra, gs); };
   auto load_plain = [&](const int r) { load_pulled<S, false>(src, geo, r, ra, gs); };
@@ -362,9 +429,9 @@ k_step2(const S* __restrict__ src, S* __restrict__ dst, Geo geo, Coef<typename S
     for (int r = y0 - 1; r <= y1; ++r) {
       phase_a(r);
       if (r < y1) load_plain(r + 1);
-      __syncthreads();
+      pair_sync();
       if (interior && r > y0) phase_b(r - 1);
-      __syncthreads();
+      pair_sync();
     }
     return;
   }
@@ -377,30 +444,30 @@ k_step2(const S* __restrict__ src, S* __restrict__ dst, Geo geo, Coef<typename S
   // at phase A, and the wait there covers every store as well.)
   phase_a(y0 - 1);
   load(y0);
-  __syncthreads();
-  __syncthreads();
+  pair_sync();
+  pair_sync();
   phase_a(y0);
   load(y0 + 1);
-  __syncthreads();
-  __syncthreads();
+  pair_sync();
+  pair_sync();
   phase_a(y0 + 1);
   if (y0 + 1 < y1) {
     load(y0 + 2);
     for (int r = y0 + 2; r < y1; ++r) {
-      __syncthreads();
+      pair_sync();
       phase_b(r - 2);
-      __syncthreads();
+      pair_sync();
       phase_a(r);
       load(r + 1);
     }
-    __syncthreads();
+    pair_sync();
     phase_b(y1 - 2);
-    __syncthreads();
+    pair_sync();
     phase_a(y1);
   }
-  __syncthreads();
+  pair_sync();
   phase_b(y1 - 1);
-  __syncthreads();
+  pair_sync();
 }
 
 // Two reverse steps per launch, staged through LDS like k_step2 (same blocks, halo
@@ -569,7 +636,7 @@ k_step_walls(const S* __restrict__ src, S* __restrict__ dst, Geo geo, Coef<typen
 #pragma unroll
     for (int i = 0; i < Q; ++i) out[i] = g[opp(i)];
   } else {
-    collide<T, MODEL, StorageTraits<S>::kShortCollide>(g, out, k, nullptr);
+    collide<T, MODEL>(g, out, k, nullptr);
   }
   char* orow = reinterpret_cast<char*>(dst) + y * rsb;
 #pragma unroll

@@ -88,12 +88,28 @@ BAD = [dict(nx=0), dict(ny=0), dict(nx=-3), dict(theta=0.0), dict(theta=1.0), di
        dict(nx=65536, ny=32768), dict(nx=65537, ny=32767), dict(nx=2 ** 31 - 63, ny=1)]
 
 
-@pytest.mark.parametrize("nx,ny", [(65536, 32767), (2 ** 31 - 64, 1), (1, 2 ** 25 - 1)])
+@pytest.mark.parametrize("nx,ny", [(65536, 32767), (59652288, 1), (1, 2 ** 25 - 1)])
 def test_largest_accepted_grids(capi, nx, ny):
     """The padded plane (nx rounded up to 64) * ny must stay below 2^31."""
     s, n = capi.lbm_workspace_bytes(_params(capi, nx=nx, ny=ny, storage="f16", pattern="aa"))
     assert s == capi.LBM_OK
     assert n >= 9 * 2 * _round_up(nx, 64) * ny
+
+
+@pytest.mark.parametrize("storage,elem", [("f64", 8), ("f32", 4), ("f16", 4), ("bf16", 4)])
+def test_row_width_limit(capi, storage, elem):
+    """Byte offsets within one lattice row are 32-bit: 9 * pitch * (larger of the storage and
+    compute element sizes) must stay below 2^31. Accepted at the widest such row (and nx one
+    node short of it), rejected one node wider, for plain and recorded runs."""
+    widest = (2 ** 31 - 1) // (9 * elem) // 64 * 64
+    assert 9 * widest * elem < 2 ** 31 <= 9 * (widest + 64) * elem
+    for rec in (0, 3):
+        for nx in (widest, widest - 1):
+            s, _ = capi.lbm_workspace_bytes(_params(capi, nx=nx, ny=1, storage=storage, record_steps=rec))
+            assert s == capi.LBM_OK, (nx, rec)
+        s, _ = capi.lbm_workspace_bytes(_params(capi, nx=widest + 1, ny=1, storage=storage, record_steps=rec))
+        assert s == capi.LBM_ERR_INVALID_ARGUMENT
+        assert "too wide" in capi.last_error()
 
 
 @pytest.mark.parametrize("bad", BAD)
