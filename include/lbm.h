@@ -153,6 +153,18 @@ lbm_status lbm_set_populations(lbm_ctx* ctx, const double* d_f);
  * LBM_ERR_NONFINITE (with out filled) if any population is NaN or infinite. */
 lbm_status lbm_invariants(lbm_ctx* ctx, double out[3]);
 
+/* For callers that cannot allocate or hand the library device memory for scratch (code
+ * around HIP graph capture, tight serving loops, harnesses that forbid allocation): the
+ * totals and status of lbm_invariants, from the same kernels in the same order (bit-identical
+ * results), with the reduction's 1024 x 4 FP64 partial sums and 4-entry result kept in a
+ * static device array of 32 800 bytes instead of the context's workspace. Allocates nothing;
+ * the library holds one such array on every device it runs on until the process ends. The
+ * array's size does not depend on the grid, so every grid lbm_init accepts fits. Every call
+ * on a device shares that device's array and overwrites it completely (nothing to clear):
+ * calls that overlap in time on one device (other contexts or streams) race and may return
+ * each other's totals. Waits for the stream. */
+lbm_status lbm_invariants_static(lbm_ctx* ctx, double out[3]);
+
 /* Discrete adjoint of the recorded run (requires record_steps = N > 0 and lbm_time = N).
  * Given dJ/drho, dJ/du_x, dJ/du_y of the moments at t = N (compute-type [ny][nx]
  * arrays; d_rho_bar may be NULL for zero), writes dJ/du_x and dJ/du_y of the initial

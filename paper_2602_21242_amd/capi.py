@@ -63,6 +63,8 @@ def lib():
         L.lbm_set_populations.argtypes = [_vp, _vp]
         L.lbm_invariants.restype = st
         L.lbm_invariants.argtypes = [_vp, ctypes.POINTER(ctypes.c_double)]
+        L.lbm_invariants_static.restype = st
+        L.lbm_invariants_static.argtypes = [_vp, ctypes.POINTER(ctypes.c_double)]
         L.lbm_adjoint.restype = st
         L.lbm_adjoint.argtypes = [_vp, _vp, _vp, _vp, _vp, _vp]
         L.lbm_adjoint_populations.restype = st
@@ -137,6 +139,12 @@ def lbm_set_populations(ctx, d_f):
 def lbm_invariants(ctx):
     out = (ctypes.c_double * 3)()
     s = lib().lbm_invariants(ctx, out)
+    return s, tuple(out)
+
+
+def lbm_invariants_static(ctx):
+    out = (ctypes.c_double * 3)()
+    s = lib().lbm_invariants_static(ctx, out)
     return s, tuple(out)
 
 

@@ -10,6 +10,8 @@
 #include <cstdlib>
 #include <cstring>
 #include <exception>
+#include <map>
+#include <mutex>
 #include <new>
 #include <string>
 
@@ -220,6 +222,7 @@ lbm_status check_ctx(const lbm_ctx* c) {
 }
 
 lbm_status step_from(lbm_ctx* c, const void* src, void* rec);
+lbm_status reduce_totals(lbm_ctx* c, double* partial, double* result, double out[3]);
 
 // One time step of the current pattern; rec != nullptr also writes the moment record. A
 // state held in a checkpoint slot is stepped out of place into population buffer 0.
@@ -610,23 +613,82 @@ lbm_status lbm_invariants(lbm_ctx* c, double out[3]) {
     if (s != LBM_OK) return s;
     if (!out) return fail(LBM_ERR_INVALID_ARGUMENT, "out is NULL");
     DeviceGuard g(c->device);
-    double* partial = reinterpret_cast<double*>(c->ws + c->plan.red_off);
-    double* result = reinterpret_cast<double*>(c->ws + c->plan.res_off);
-    s = dispatch(c->p.storage, [&](auto eng) -> lbm_status {
-      using E = decltype(eng);
-      hipError_t e = E::invariants(c->d, c->layout(c->time), c->state(), partial, result, c->stream);
-      if (e != hipSuccess) return fail(LBM_ERR_HIP, std::string("reduction kernel launch: ") + hipGetErrorString(e));
-      return LBM_OK;
-    });
-    if (s != LBM_OK) return s;
-    double host[4];
-    HIP_TRY(hipMemcpyAsync(host, result, sizeof(host), hipMemcpyDeviceToHost, c->stream));
-    HIP_TRY(hipStreamSynchronize(c->stream));
-    out[0] = host[0];
-    out[1] = host[1];
-    out[2] = host[2];
-    if (host[3] > 0.0) return fail(LBM_ERR_NONFINITE, std::to_string(int64_t(host[3])) + " nodes hold non-finite populations");
+    return reduce_totals(c, reinterpret_cast<double*>(c->ws + c->plan.red_off),
+                         reinterpret_cast<double*>(c->ws + c->plan.res_off), out);
+  });
+}
+
+}  // extern "C"
+
+namespace {
+
+// Reduction scratch of lbm_invariants_static: kReduceBlocks x 4 FP64 partial sums followed by
+// the 4-entry result (sum rho, sum rho u_x, sum rho u_y, non-finite count). Every device the
+// library runs on holds its own copy until the process ends. In host code `scratch` names a
+// host-side stand-in, not device memory: kernels and copies use the address that
+// hipGetSymbolAddress returns for the current device, kept per device below.
+constexpr size_t kStaticScratchDoubles = size_t(lbm::kReduceBlocks) * 4 + 4;
+static __device__ __align__(256) double scratch[kStaticScratchDoubles];
+
+std::mutex g_scratch_mu;
+std::map<int, double*> g_scratch_ptr;
+
+// Device address of `dev`'s copy of the scratch array, looked up once per device with that
+// device current (the caller makes it current).
+lbm_status static_scratch(int dev, double** out) {
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  auto it = g_scratch_ptr.find(dev);
+  if (it == g_scratch_ptr.end()) {
+    double* ptr = nullptr;
+    const hipError_t e = hipGetSymbolAddress(reinterpret_cast<void**>(&ptr), HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !ptr)
+      return fail(LBM_ERR_HIP, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+    it = g_scratch_ptr.emplace(dev, ptr).first;
+  }
+  *out = it->second;
+  return LBM_OK;
+}
+
+// The two reduction kernels of the FP64 totals with their partials and result at `partial`
+// and `result`, then the result copied to the host after the stream has drained.
+lbm_status reduce_totals(lbm_ctx* c, double* partial, double* result, double out[3]) {
+  lbm_status s = dispatch(c->p.storage, [&](auto eng) -> lbm_status {
+    using E = decltype(eng);
+    hipError_t e = E::invariants(c->d, c->layout(c->time), c->state(), partial, result, c->stream);
+    if (e != hipSuccess) return fail(LBM_ERR_HIP, std::string("reduction kernel launch: ") + hipGetErrorString(e));
     return LBM_OK;
+  });
+  if (s != LBM_OK) return s;
+  double host[4];
+  HIP_TRY(hipMemcpyAsync(host, result, sizeof(host), hipMemcpyDeviceToHost, c->stream));
+  HIP_TRY(hipStreamSynchronize(c->stream));
+  out[0] = host[0];
+  out[1] = host[1];
+  out[2] = host[2];
+  if (host[3] > 0.0) return fail(LBM_ERR_NONFINITE, std::to_string(int64_t(host[3])) + " nodes hold non-finite populations");
+  return LBM_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+lbm_status lbm_invariants_static(lbm_ctx* c, double out[3]) {
+  return guarded([&]() -> lbm_status {
+    lbm_status s = check_ctx(c);
+    if (s != LBM_OK) return s;
+    if (!out) return fail(LBM_ERR_INVALID_ARGUMENT, "out is NULL");
+    DeviceGuard g(c->device);
+    double* ptr = nullptr;
+    s = static_scratch(c->device, &ptr);
+    if (s != LBM_OK) return s;
+    // The partial count is fixed (it does not grow with the grid), so every grid lbm_init
+    // accepts fits the array; the check guards the layout itself.
+    if (size_t(lbm::kReduceBlocks) * 4 + 4 > kStaticScratchDoubles)
+      return fail(LBM_ERR_UNSUPPORTED, "reduction partials exceed the static scratch array");
+    // Every partial and the result are written by the kernels before they are read, so the
+    // array needs no clearing between calls.
+    return reduce_totals(c, ptr, ptr + size_t(lbm::kReduceBlocks) * 4, out);
   });
 }
 
