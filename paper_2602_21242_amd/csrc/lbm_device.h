@@ -36,6 +36,22 @@ __device__ __forceinline__ T sel(int c, T m, T z, T p) { return c < 0 ? m : (c >
 
 // ---------------------------------------------------------------------------------------
 // Storage element types and conversions (round to nearest even into 16-bit types).
+
+// x rounded to FP32 with round-to-odd: the FP32 value next to x toward zero, its last
+// significand bit set when x is not representable. Rounding that to a format of at most 22
+// significand bits to nearest even gives the correctly rounded value of x itself (the odd
+// bit stands for everything below the FP32 grid, so no tie is created or lost): FP16 has 11,
+// BF16 8. Converting through a nearest-even FP32 instead rounds twice and can land on the
+// wrong neighbour when x lies within half an FP32 ulp of a 16-bit tie.
+__device__ __forceinline__ float f64_to_f32_odd(double x) {
+  float f = float(x);
+  const double fd = double(f);
+  if (fd == x) return f;
+  uint32_t b = __builtin_bit_cast(uint32_t, f);
+  if (__builtin_fabs(fd) > __builtin_fabs(x)) b -= 1u;  // nearest was away from zero: step back
+  return __builtin_bit_cast(float, b | 1u);
+}
+
 template <class S> struct StorageTraits;
 template <> struct StorageTraits<double> {
   using T = double;
@@ -43,6 +59,7 @@ template <> struct StorageTraits<double> {
   static __device__ __forceinline__ double load(double v) { return v; }
   static __device__ __forceinline__ double load_raw(double v) { return v; }
   static __device__ __forceinline__ double store(double v) { return v; }
+  static __device__ __forceinline__ double from_f64(double v) { return v; }
 };
 template <> struct StorageTraits<float> {
   using T = float;
@@ -50,6 +67,7 @@ template <> struct StorageTraits<float> {
   static __device__ __forceinline__ float load(float v) { return v; }
   static __device__ __forceinline__ float load_raw(float v) { return v; }
   static __device__ __forceinline__ float store(float v) { return v; }
+  static __device__ __forceinline__ float from_f64(double v) { return float(v); }
 };
 template <> struct StorageTraits<_Float16> {
   using T = float;
@@ -63,6 +81,7 @@ template <> struct StorageTraits<_Float16> {
     return float(__builtin_bit_cast(_Float16, uint16_t(r)));
   }
   static __device__ __forceinline__ _Float16 store(float v) { return _Float16(v); }
+  static __device__ __forceinline__ _Float16 from_f64(double v) { return _Float16(f64_to_f32_odd(v)); }
 };
 // bfloat16 as its raw 16 bits; stores convert with the hardware FP32 -> BF16 conversion
 // (round to nearest even).
@@ -78,6 +97,7 @@ template <> struct StorageTraits<bf16_t> {
     __builtin_memcpy(&r.bits, &h, sizeof(r.bits));
     return r;
   }
+  static __device__ __forceinline__ bf16_t from_f64(double v) { return store(f64_to_f32_odd(v)); }
 };
 
 // ---------------------------------------------------------------------------------------

@@ -88,8 +88,9 @@ __device__ __forceinline__ Tile tile_of(const RunDesc& d) {
 }
 
 
-// f^0 = f^eq(rho, u) of the guided equilibrium (eq:guidedEq), stored shifted, computed in FP64
-// as drho Phi_x Phi_y + rho0 (d_x Phi_y + r_x d_y) (no cancellation against w_i rho0).
+// f^0 = f^eq(rho, u) of the guided equilibrium (eq:guidedEq), stored shifted, computed from
+// the caller's FP64 fields in FP64 as drho Phi_x Phi_y + rho0 (d_x Phi_y + r_x d_y) (no
+// cancellation against w_i rho0) and rounded once to the storage type.
 template <class S>
 __global__ void __launch_bounds__(kBlock)
 k_init(S* buf, RunDesc d, LayoutSel L, const double* rho, const double* ux, const double* uy) {
@@ -119,10 +120,12 @@ k_init(S* buf, RunDesc d, LayoutSel L, const double* rho, const double* ux, cons
     const int a = cx(i) + 1, b = cy(i) + 1;
     const double hx = rr[a] + dx[a], hy = rr[b] + dy[b];
     const double feqs = drho * hx * hy + d.rho0 * (dx[a] * hy + rr[a] * dy[b]);
-    buf[layout_index(i, x, y, d, L)] = Tr::store(typename Tr::T(feqs));
+    buf[layout_index(i, x, y, d, L)] = Tr::from_f64(feqs);
   }
 }
 
+// Export to FP64 or FP32: f = g + w rho0 in FP64 (exact for every storage type's g before the
+// addition), rounded once to the output type.
 template <class S, class O>
 __global__ void __launch_bounds__(kBlock)
 k_get(const S* buf, RunDesc d, LayoutSel L, O* out) {
@@ -150,6 +153,8 @@ k_get(const S* buf, RunDesc d, LayoutSel L, O* out) {
   }
 }
 
+// Import of the caller's FP64 populations: g = f - w rho0 in FP64, rounded once to the
+// storage type.
 template <class S>
 __global__ void __launch_bounds__(kBlock)
 k_set(S* buf, RunDesc d, LayoutSel L, const double* in) {
@@ -171,40 +176,43 @@ k_set(S* buf, RunDesc d, LayoutSel L, const double* in) {
 #pragma unroll
   for (int i = 0; i < Q; ++i) {
     const double wt = (cx(i) == 0 ? 1.0 - th : 0.5 * th) * (cy(i) == 0 ? 1.0 - th : 0.5 * th);
-    buf[layout_index(i, x, y, d, L)] = Tr::store(typename Tr::T(sh[i][w][lane] - wt * d.rho0));
+    buf[layout_index(i, x, y, d, L)] = Tr::from_f64(sh[i][w][lane] - wt * d.rho0);
   }
 }
 
-// rho, j of one node from the stored state, accumulated in FP64.
-template <class S>
+// rho - rho0 and j of one node from the stored state, accumulated in A: FP64 for the global
+// totals, the compute type for everything else.
+template <class A, class S>
 __device__ __forceinline__ void node_moments(const S* buf, const RunDesc& d, LayoutSel L, int x, int y,
-                                             double& drho, double& jx, double& jy, bool* bad = nullptr) {
+                                             A& drho, A& jx, A& jy, bool* bad = nullptr) {
   using Tr = StorageTraits<S>;
-  drho = jx = jy = 0.0;
+  drho = jx = jy = A(0);
   bool nf = false;
 #pragma unroll
   for (int i = 0; i < Q; ++i) {
-    const double g = double(Tr::load(buf[layout_index(i, x, y, d, L)]));
+    const A g = A(Tr::load(buf[layout_index(i, x, y, d, L)]));
     nf |= !isfinite(g);
     drho += g;
-    jx += cx(i) * g;
-    jy += cy(i) * g;
+    jx += A(cx(i)) * g;
+    jy += A(cy(i)) * g;
   }
   if (bad) *bad = nf;
 }
 
+// rho and u = j / rho of every node, in the compute type, written as O.
 template <class S, class O>
 __global__ void __launch_bounds__(kBlock)
 k_moments(const S* buf, RunDesc d, LayoutSel L, O* rho, O* ux, O* uy) {
+  using T = typename StorageTraits<S>::T;
   __shared__ O sh[3][kTileGroups][kLanes];
   const Tile tl = tile_of(d);
   if (tl.y >= d.ny) return;  // whole block
   const int w = int(threadIdx.x) / kLanes, lane = int(threadIdx.x) % kLanes;
   const int s = tl.s0 + w, x = lane * tl.S + s, y = tl.y;
   if (s < tl.S && x < d.nx) {
-    double drho, jx, jy;
+    T drho, jx, jy;
     node_moments(buf, d, L, x, y, drho, jx, jy);
-    const double r = d.rho0 + drho;
+    const T r = T(d.rho0) + drho;
     sh[0][w][lane] = O(r);
     sh[1][w][lane] = O(jx / r);
     sh[2][w][lane] = O(jy / r);
@@ -230,7 +238,7 @@ k_reduce_partial(const S* buf, RunDesc d, LayoutSel L, double* partial) {
     if (!storage_node(t, d, y, q, x)) continue;
     double drho, jx, jy;
     bool bad;
-    node_moments(buf, d, L, x, y, drho, jx, jy, &bad);
+    node_moments<double>(buf, d, L, x, y, drho, jx, jy, &bad);
     s0 += drho;
     s1 += jx;
     s2 += jy;
@@ -293,10 +301,10 @@ k_seed(const S* buf, RunDesc d, LayoutSel L, const T* rhob, const T* uxb, const 
   const int s = tl.s0 + w, x = lane * tl.S + s, y = tl.y;
   if (s >= tl.S || x >= d.nx) return;
   const int q = s * kLanes + lane;
-  double drho, jx, jy;
+  T drho, jx, jy;
   node_moments(buf, d, L, x, y, drho, jx, jy);
-  const T r = T(d.rho0 + drho);
-  const T vx = T(jx / (d.rho0 + drho)), vy = T(jy / (d.rho0 + drho));
+  const T r = T(d.rho0) + drho;
+  const T vx = jx / r, vy = jy / r;
   const T rb = sh[0][w][lane];
   const T ax = sh[1][w][lane] / r, ay = sh[2][w][lane] / r;
 #pragma unroll
@@ -337,10 +345,10 @@ k_ic_adjoint(const S* buf0, RunDesc d, LayoutSel L, const T* fbar, T* uxb, T* uy
   const int s = tl.s0 + w, x = lane * tl.S + s, y = tl.y;
   if (s < tl.S && x < d.nx) {
     const int q = s * kLanes + lane;
-    double drho, jx, jy;
+    T drho, jx, jy;
     node_moments(buf0, d, L, x, y, drho, jx, jy);
-    const T r = T(d.rho0 + drho);
-    const T vx = T(jx / (d.rho0 + drho)), vy = T(jy / (d.rho0 + drho));
+    const T r = T(d.rho0) + drho;
+    const T vx = jx / r, vy = jy / r;
     const T th = T(d.theta);
     const T hx[3] = {T(0.5) * (th + vx * vx - vx), T(1) - th - vx * vx, T(0.5) * (th + vx * vx + vx)};
     const T hy[3] = {T(0.5) * (th + vy * vy - vy), T(1) - th - vy * vy, T(0.5) * (th + vy * vy + vy)};

@@ -63,3 +63,51 @@ def test_storage_round_trip_is_rne(storage, pattern):
         print(f"mismatch at {i}: got-w {got[i] - w[i[0], 0, 0]:.9e} expected-w {gs[i]:.9e} g32 {g32[i]:.9e}")
     assert bad.shape[0] == 0, f"{bad.shape[0]} of {got.size} values differ"
 
+
+
+def _f64_to_bf16_rne(x):
+    """Correctly rounded FP64 -> BF16 (nearest, ties to even) on the FP64 bit pattern: BF16 keeps
+    8 significand bits, so 45 of the 53 are rounded off (normal range only)."""
+    u = np.abs(x).view(np.uint64)
+    u = (u + np.uint64((1 << 44) - 1) + ((u >> np.uint64(45)) & np.uint64(1))) >> np.uint64(45) << np.uint64(45)
+    return np.copysign(u.view(np.float64), x)
+
+
+def _near_ties(storage, n, seed):
+    """Shifted values within half an FP32 ulp of a tie between two 16-bit neighbours: rounding
+    through a nearest-even FP32 first lands exactly on the tie and then on the even neighbour,
+    while a single rounding of the FP64 value goes to the nearer one."""
+    rng = np.random.default_rng(seed)
+    if storage == "f16":
+        a = (rng.standard_normal(n) * 10.0 ** rng.uniform(-3, -1, size=n)).astype(np.float16)
+        a = a[np.isfinite(a) & (np.abs(a) >= np.finfo(np.float16).tiny)]  # normal range
+        b = np.nextafter(a, np.float16(np.inf))
+        t = (a.astype(np.float64) + b.astype(np.float64)) / 2
+    else:
+        hi = rng.integers(0x3C00, 0x3E00, size=n, dtype=np.uint32)   # |g| in about [0.008, 0.125)
+        t = ((hi << 16) | 0x8000).view(np.float32).astype(np.float64) * np.where(rng.random(n) < 0.5, -1, 1)
+    ulp32 = np.spacing(np.abs(t).astype(np.float32)).astype(np.float64)
+    # short binary fractions of an FP32 ulp, so that f = g + w rho0 stays exact in FP64
+    frac = rng.choice([-0.375, -0.25, 0.25, 0.375], size=t.size)
+    return t + frac * ulp32
+
+
+@pytest.mark.parametrize("storage", ["f16", "bf16"])
+def test_import_rounds_fp64_once(storage):
+    """lbm_set_populations rounds g = f - w rho0 (formed in FP64) once, directly to the 16-bit
+    type: on values within half an FP32 ulp of a 16-bit tie the result is the nearer neighbour,
+    which rounding through FP32 would miss. theta = 1/2 keeps f - w rho0 exact in FP64."""
+    nx, ny, th = 48, 10, 0.5
+    w = _rest_weights(th)[:, None, None]
+    vals = _near_ties(storage, 9 * nx * ny, seed=3)
+    g = np.resize(vals, (9, ny, nx))
+    f = g + w
+    assert np.array_equal(f - w, g)
+    sim = gpu_sim(nx, ny, th, 0.02, "complete", storage, "ab", f0=f)
+    got = sim.populations().cpu().numpy() - w
+    exp = g.astype(np.float16).astype(np.float64) if storage == "f16" else _f64_to_bf16_rne(g)
+    twice = (g.astype(np.float32).astype(np.float16).astype(np.float64) if storage == "f16"
+             else _to_bf16_rne(g.astype(np.float32)).astype(np.float64))
+    assert np.count_nonzero(twice != exp) > g.size // 4  # the inputs do separate the two roundings
+    bad = np.argwhere(got != exp)
+    assert bad.shape[0] == 0, f"{bad.shape[0]} of {got.size} values differ, e.g. {tuple(bad[0])}"
