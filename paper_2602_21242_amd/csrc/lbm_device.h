@@ -16,6 +16,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <type_traits>
+
 namespace lbm {
 
 constexpr int Q = 9;
@@ -100,6 +102,13 @@ template <> struct StorageTraits<bf16_t> {
   static __device__ __forceinline__ bf16_t from_f64(double v) { return store(f64_to_f32_odd(v)); }
 };
 
+// Whether the collision takes the rest population and populations 1 and 2 from the
+// conservation of mass and momentum (see collide): FP32 storage. FP64 rounds 2^29 times finer;
+// for 16-bit storage the rounding of every stored population outweighs it, and it measured
+// slightly worse there (FP16, 8192^2 turbulence after 5000 steps: 2.25e-3 against 2.04e-3).
+template <class S> struct ConserveExactly : std::false_type {};
+template <> struct ConserveExactly<float> : std::true_type {};
+
 // ---------------------------------------------------------------------------------------
 // Per-run constants, computed on the host in FP64 and rounded to the compute type.
 template <class T>
@@ -130,6 +139,18 @@ __device__ __forceinline__ float recip<float>(float x) {
   return __builtin_fmaf(r, __builtin_fmaf(-x, r, 1.0f), r);
 }
 
+// Post-collision populations 1, 2 (with MOMENTUM) and 0 recomputed from the node's mass excess
+// drho and momentum j: sum_i g*_i = drho, sum_i c_i g*_i = j.
+template <class T, bool MOMENTUM>
+__device__ __forceinline__ void conserve(T drho, T jx, T jy, T out[Q]) {
+  const T d57 = out[5] - out[7], d68 = out[6] - out[8];
+  if (MOMENTUM) {
+    out[1] = jx - ((d57 - d68) - out[3]);
+    out[2] = jy - ((d57 + d68) - out[4]);
+  }
+  out[0] = drho - (((out[1] + out[3]) + (out[2] + out[4])) + ((out[5] + out[7]) + (out[6] + out[8])));
+}
+
 // ---------------------------------------------------------------------------------------
 // Collision of one node on shifted populations: g -> g* (eq:lbe, first line, with the
 // non-equilibrium part of the chosen model). Optionally returns the recorded moments.
@@ -144,7 +165,22 @@ __device__ __forceinline__ float recip<float>(float x) {
 // P_i = Phi_x Phi_y, needs about six; with the two-step kernel's buffer accesses the short form
 // measured faster for every storage type on MI355X: FP32 pair 150.1 -> 153.6 GLUPS at 4096^2,
 // 152.2 -> 156.8 at 8192^2, FP64 pair 77.3 -> 78.5.)
-template <class T, int MODEL>
+//
+// With CONSERVE the populations 0, 1 and 2 are then taken from the conservation laws the
+// collision obeys (eq:density-momentum; the corrections keep them, eq:genOReg-constraints):
+// the post-collision mass and momentum equal the pre-collision drho and j, so
+// g*_1 = j_x - (g*_5 - g*_7 - g*_6 + g*_8 - g*_3), g*_2 = j_y - (g*_5 - g*_7 + g*_6 - g*_8 - g*_4)
+// and g*_0 = drho - sum_{i > 0} g*_i, which equal the values above in exact arithmetic. Rounded
+// to FP32, the nine values of the direct form do not sum to drho and j exactly, and the excess
+// is a smooth function of the node's state: wherever the flow is nearly uniform over large
+// regions it has the same sign at every node and every step, and mass and momentum drift
+// linearly. On the 16384 x 4096 double shear layer (bands at u_x = +-0.2) the FP32 run gained
+// 1e-6 of its mass and 2e-5 of its kinetic energy in 3000 steps, and its populations drifted
+// from the FP64 run's by 1.7e-5 (theta = 1/3) and 2.5e-5 (0.5) of max f; taken from the
+// conservation laws, the drifts are 1e-11 and 1e-8 and the populations stay within 2.7e-6
+// and 6.4e-7 (4096^2 Taylor-Green after 2000 steps: 2.1e-6 -> 1.2e-7). The uncorrected model
+// does not conserve momentum (Sec. 3), so only its mass is taken this way.
+template <class T, int MODEL, bool CONSERVE = false>
 __device__ __forceinline__ void collide(const T g[Q], T out[Q], const Coef<T>& k, T rec[NREC]) {
   // Moments (Sec. 1): rho = rho0 + sum g, j = sum c g, D = sum (cx^2 - cy^2) g, Pxy = sum cx cy g.
   const T s13 = g[1] + g[3], s24 = g[2] + g[4], s57 = g[5] + g[7], s68 = g[6] + g[8];
@@ -185,6 +221,7 @@ __device__ __forceinline__ void collide(const T g[Q], T out[Q], const Coef<T>& k
       const T feqs = hy * sel(cx(i), Km, K0, Kp) + rdy;
       out[i] = feqs + k.omb * (g[i] - feqs);
     }
+    if constexpr (CONSERVE) conserve<T, true>(drho, jx, jy, out);
     if (rec) rec[3] = rec[4] = T(0);
     return;
   }
@@ -255,6 +292,7 @@ __device__ __forceinline__ void collide(const T g[Q], T out[Q], const Coef<T>& k
     const T v = sel(cx(i), Cxm, Cx0, Cxp) * sel(cy(i), Y2m, Y20, Y2p) - sel(cy(i), Y1m, Y10, Y1p);
     out[i] = hy * (sel(cx(i), Km, K0, Kp) + hx * v) + (rdy + Psi[i]);
   }
+  if constexpr (CONSERVE) conserve<T, MODEL != M_UC>(drho, jx, jy, out);
 }
 
 // ---------------------------------------------------------------------------------------

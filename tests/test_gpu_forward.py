@@ -139,8 +139,8 @@ def test_uniform_flow_stays_fixed_fp32(model, theta):
     FP32 the per-axis rest factors 1 - theta and theta/2 must satisfy r0 + 2 r1 = 1 exactly:
     the equilibrium's momentum is rho u (r0 + 2 r1), so an excess e = 3e-8 (theta = 1/3,
     correctly rounded factors) would multiply u by (1 + e)^2000 = 1 + 6e-5 here. What remains
-    is FP32 rounding noise in N and the corrections of the uniform state, at most 1.2e-6
-    over the 2000 steps (complete model, theta = 0.55); the bound is 5e-6."""
+    is FP32 rounding noise in N and the corrections of the uniform state, at most 8.9e-8
+    over the 2000 steps (complete model, theta = 0.3); the bound is 5e-6."""
     nx, ny, U, V, n = 40, 24, 0.08, -0.05, 2000
     fields = (np.ones((ny, nx)), np.full((ny, nx), U), np.full((ny, nx), V))
     sim = gpu_sim(nx, ny, theta, 0.01, model, "f32", "ab", fields=fields)

@@ -10,8 +10,8 @@ with a relative error of up to 2^-11 (FP16) or 2^-8 (BF16), and at tau = 0.5003 
 and shear modes are hardly damped, so the stored noise walks. Measured on MI355X (complete
 model): FP16 4.8e-4 / 9.1e-4 / 1.06e-3 / 2.04e-3 after 100 / 700 / 1000 / 5000 steps,
 carried by the momentum (max |delta j| 2.5e-3 at 1000 steps against 8.6e-4 for the
-deviatoric stress); BF16 4.7e-3 / 1.0e-2 / 1.3e-2 / 5.5e-2; FP32 6.3e-7 / 7.0e-7 / 7.7e-7 /
-9.8e-7. LBGK with FP16 storage: 1.5e-3 / 2.5e-3 / 3.0e-3 / 3.0e-3, the regularised model
+deviatoric stress); BF16 4.7e-3 / 1.0e-2 / 1.3e-2 / 5.5e-2; FP32 2.2e-7 / 3.8e-7 / 3.6e-7 /
+4.2e-7. LBGK with FP16 storage: 1.5e-3 / 2.5e-3 / 3.0e-3 / 3.0e-3, the regularised model
 removing the non-hydrodynamic part of the stored noise every step where LBGK keeps it.
 
 So the FP16 bar eps_f <= 1e-3 holds over the first 700 steps of this workload, and later
