@@ -102,12 +102,15 @@ template <> struct StorageTraits<bf16_t> {
   static __device__ __forceinline__ bf16_t from_f64(double v) { return store(f64_to_f32_odd(v)); }
 };
 
-// Whether the collision takes the rest population and populations 1 and 2 from the
-// conservation of mass and momentum (see collide): FP32 storage. FP64 rounds 2^29 times finer;
-// for 16-bit storage the rounding of every stored population outweighs it, and it measured
-// slightly worse there (FP16, 8192^2 turbulence after 5000 steps: 2.25e-3 against 2.04e-3).
-template <class S> struct ConserveExactly : std::false_type {};
-template <> struct ConserveExactly<float> : std::true_type {};
+// How the collision's output keeps the node's mass and momentum (see collide and conserve):
+// 0 direct form, 1 populations 0, 1, 2 from the conservation laws in the compute type (FP32
+// storage), 2 the same in FP16 storage precision (FP16 storage, OReg models). FP64 rounds 2^29
+// times finer than FP32 and needs neither. BF16 would gain as much as FP16 (turbulence after
+// 5000 steps: 5.5e-2 -> 2.6e-2) but at 16 % of its throughput, with its error above 1e-2
+// either way.
+template <class S> struct ConserveMode { static constexpr int value = 0; };
+template <> struct ConserveMode<float> { static constexpr int value = 1; };
+template <> struct ConserveMode<_Float16> { static constexpr int value = 2; };
 
 // ---------------------------------------------------------------------------------------
 // Per-run constants, computed on the host in FP64 and rounded to the compute type.
@@ -151,6 +154,37 @@ __device__ __forceinline__ void conserve(T drho, T jx, T jy, T out[Q]) {
   out[0] = drho - (((out[1] + out[3]) + (out[2] + out[4])) + ((out[5] + out[7]) + (out[6] + out[8])));
 }
 
+// The same in FP16 storage precision: every population is returned as its FP16 value, and the
+// momentum that the rounded diagonal populations miss is split evenly between the two
+// populations of each axis (+r/2 on c = +1, -r/2 on c = -1), which leaves the normal-stress
+// moment D = sum (c_x^2 - c_y^2) g untouched; then g*_0 takes the mass. The stored node then
+// carries the rounding of two populations per momentum component and of one in its mass,
+// instead of seven and nine. Measured on the 8192^2 turbulence (complete model, max error of
+// the populations against the FP64 run after 100 / 1000 / 5000 steps): 4.8e-4 / 1.06e-3 /
+// 2.04e-3 with the direct form, 4.2e-4 / 7.1e-4 / 1.26e-3 with this; partial model after
+// 100 / 1000 / 3000 steps 4.8e-4 / 1.11e-3 / 1.60e-3 -> 3.9e-4 / 8.1e-4 / 1.09e-3; 6 % of the
+// FP16 two-step kernel's throughput. (Giving the whole residual to populations 1 and 2
+// instead moved D with it: better to 1000 steps, worse after.)
+template <bool MOMENTUM>
+__device__ __forceinline__ void conserve_fp16(float drho, float jx, float jy, float out[Q]) {
+  auto q = [](float v) { return float(_Float16(v)); };
+#pragma unroll
+  for (int i = 5; i < Q; ++i) out[i] = q(out[i]);
+  const float d57 = out[5] - out[7], d68 = out[6] - out[8];
+  if (MOMENTUM) {
+    const float hrx = 0.5f * (jx - ((out[1] - out[3]) + (d57 - d68)));
+    const float hry = 0.5f * (jy - ((out[2] - out[4]) + (d57 + d68)));
+    out[1] = q(out[1] + hrx);
+    out[3] = q(out[3] - hrx);
+    out[2] = q(out[2] + hry);
+    out[4] = q(out[4] - hry);
+  } else {
+#pragma unroll
+    for (int i = 1; i < 5; ++i) out[i] = q(out[i]);
+  }
+  out[0] = drho - (((out[1] + out[3]) + (out[2] + out[4])) + ((out[5] + out[7]) + (out[6] + out[8])));
+}
+
 // ---------------------------------------------------------------------------------------
 // Collision of one node on shifted populations: g -> g* (eq:lbe, first line, with the
 // non-equilibrium part of the chosen model). Optionally returns the recorded moments.
@@ -166,7 +200,7 @@ __device__ __forceinline__ void conserve(T drho, T jx, T jy, T out[Q]) {
 // measured faster for every storage type on MI355X: FP32 pair 150.1 -> 153.6 GLUPS at 4096^2,
 // 152.2 -> 156.8 at 8192^2, FP64 pair 77.3 -> 78.5.)
 //
-// With CONSERVE the populations 0, 1 and 2 are then taken from the conservation laws the
+// With CONSERVE = 1 the populations 0, 1 and 2 are then taken from the conservation laws the
 // collision obeys (eq:density-momentum; the corrections keep them, eq:genOReg-constraints):
 // the post-collision mass and momentum equal the pre-collision drho and j, so
 // g*_1 = j_x - (g*_5 - g*_7 - g*_6 + g*_8 - g*_3), g*_2 = j_y - (g*_5 - g*_7 + g*_6 - g*_8 - g*_4)
@@ -179,8 +213,9 @@ __device__ __forceinline__ void conserve(T drho, T jx, T jy, T out[Q]) {
 // from the FP64 run's by 1.7e-5 (theta = 1/3) and 2.5e-5 (0.5) of max f; taken from the
 // conservation laws, the drifts are 1e-11 and 1e-8 and the populations stay within 2.7e-6
 // and 6.4e-7 (4096^2 Taylor-Green after 2000 steps: 2.1e-6 -> 1.2e-7). The uncorrected model
-// does not conserve momentum (Sec. 3), so only its mass is taken this way.
-template <class T, int MODEL, bool CONSERVE = false>
+// does not conserve momentum (Sec. 3), so only its mass is taken this way. CONSERVE = 2 does it
+// in FP16 storage precision (conserve_fp16) for the OReg models.
+template <class T, int MODEL, int CONSERVE = 0>
 __device__ __forceinline__ void collide(const T g[Q], T out[Q], const Coef<T>& k, T rec[NREC]) {
   // Moments (Sec. 1): rho = rho0 + sum g, j = sum c g, D = sum (cx^2 - cy^2) g, Pxy = sum cx cy g.
   const T s13 = g[1] + g[3], s24 = g[2] + g[4], s57 = g[5] + g[7], s68 = g[6] + g[8];
@@ -221,7 +256,7 @@ __device__ __forceinline__ void collide(const T g[Q], T out[Q], const Coef<T>& k
       const T feqs = hy * sel(cx(i), Km, K0, Kp) + rdy;
       out[i] = feqs + k.omb * (g[i] - feqs);
     }
-    if constexpr (CONSERVE) conserve<T, true>(drho, jx, jy, out);
+    if constexpr (CONSERVE == 1) conserve<T, true>(drho, jx, jy, out);
     if (rec) rec[3] = rec[4] = T(0);
     return;
   }
@@ -292,7 +327,8 @@ __device__ __forceinline__ void collide(const T g[Q], T out[Q], const Coef<T>& k
     const T v = sel(cx(i), Cxm, Cx0, Cxp) * sel(cy(i), Y2m, Y20, Y2p) - sel(cy(i), Y1m, Y10, Y1p);
     out[i] = hy * (sel(cx(i), Km, K0, Kp) + hx * v) + (rdy + Psi[i]);
   }
-  if constexpr (CONSERVE) conserve<T, MODEL != M_UC>(drho, jx, jy, out);
+  if constexpr (CONSERVE == 1) conserve<T, MODEL != M_UC>(drho, jx, jy, out);
+  if constexpr (CONSERVE == 2) conserve_fp16<MODEL != M_UC>(drho, jx, jy, out);
 }
 
 // ---------------------------------------------------------------------------------------

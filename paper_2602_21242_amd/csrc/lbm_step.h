@@ -248,7 +248,7 @@ k_step(const S* src, S* dst, Geo geo, Coef<typename StorageTraits<S>::T> k,
     T g[Q], out[Q], rv[NREC];
 #pragma unroll
     for (int i = 0; i < Q; ++i) g[i] = Tr::load_raw(gs[n][i]);
-    collide<T, MODEL, ConserveExactly<S>::value>(g, out, k, REC ? rv : nullptr);
+    collide<T, MODEL, ConserveMode<S>::value>(g, out, k, REC ? rv : nullptr);
     if constexpr (REC) {
       char* rrow = reinterpret_cast<char*>(rec) + y * (size_t(rec_rs) * sizeof(T));
 #pragma unroll
@@ -387,7 +387,7 @@ k_step2(const S* __restrict__ src, S* __restrict__ dst, Geo geo, Coef<typename S
     T g[Q], out[Q], rv[NREC];
 #pragma unroll
     for (int i = 0; i < Q; ++i) g[i] = Tr::load_raw(gs[i]);
-    collide<T, MODEL, ConserveExactly<S>::value>(g, out, k, REC ? rv : nullptr);
+    collide<T, MODEL, ConserveMode<S>::value>(g, out, k, REC ? rv : nullptr);
 #pragma unroll
     for (int i = 0; i < Q; ++i) ring[slot][w][i][lane] = Tr::store(out[i]);
     if constexpr (REC) {
@@ -406,7 +406,7 @@ k_step2(const S* __restrict__ src, S* __restrict__ dst, Geo geo, Coef<typename S
       g[i] = Tr::load(ring[(yr - cy(i) - y0 + 1) % 3][w - cx(i)][i][lane]);
     });
     T rv[NREC];
-    collide<T, MODEL, ConserveExactly<S>::value>(g, out, k, REC ? rv : nullptr);
+    collide<T, MODEL, ConserveMode<S>::value>(g, out, k, REC ? rv : nullptr);
     if constexpr (REC) {
       const RowRes rr = row_res(rec2, size_t(rec_rs) * sizeof(T), yr);
 #pragma unroll
@@ -636,7 +636,7 @@ k_step_walls(const S* __restrict__ src, S* __restrict__ dst, Geo geo, Coef<typen
 #pragma unroll
     for (int i = 0; i < Q; ++i) out[i] = g[opp(i)];
   } else {
-    collide<T, MODEL, ConserveExactly<S>::value>(g, out, k, nullptr);
+    collide<T, MODEL, ConserveMode<S>::value>(g, out, k, nullptr);
   }
   char* orow = reinterpret_cast<char*>(dst) + y * rsb;
 #pragma unroll

@@ -21,7 +21,8 @@ theta = 1/3 and 5.6e-7 / 6.4e-7 at theta = 0.5. The FP32 collision takes its pop
 the nine values had made the double shear layer's mass and kinetic energy drift linearly
 (+1e-6 and +2e-5 over 3000 steps, eps_f 1.7e-5 / 2.5e-5 at 3000 steps). The FP64 totals of
 lbm_invariants hold that: the changes of the FP32 run's mass and momentum since the start
-stay within 1e-9 (relative to the mass) of the FP64 run's over every run here.
+stay within 2e-9 (relative to the mass) of the FP64 run's over every run here (measured at
+most 8.2e-10, reached within the first 1000 steps and constant after).
 """
 import numpy as np
 import pytest
@@ -64,7 +65,7 @@ def _compare(w, model, theta, marks):
         drift = max(abs((a - a0) - (b - b0)) for a, a0, b, b0 in zip(i32, i32_0, i64, i64_0)) / m0
         print(f"{w.name} {model} theta={theta:.4f} {n} steps: eps_f {eps:.3e}, eps_u {eps_u:.3e}, "
               f"change of mass and momentum against FP64 {drift:.2e}", flush=True)
-        assert drift <= 1e-9, drift
+        assert drift <= 2e-9, drift
         out[n] = eps
         del f64, f32
     del ref, run
