@@ -31,7 +31,12 @@
  *    unspecified; lbm_destroy is still valid. Non-finite populations are not checked per
  *    step; lbm_invariants reports them.
  *  - Compute type: FP64 when storage is LBM_F64, FP32 otherwise. Adjoint inputs and
- *    outputs use the compute type.
+ *    outputs use the compute type. Stores round to nearest even. With LBM_F32 storage the
+ *    collision takes populations 0, 1 and 2 from mass and momentum conservation (the same
+ *    values in exact arithmetic), so FP32 rounding adds no drift of mass or momentum; with
+ *    LBM_F16 storage and the OReg models it does so in FP16 precision (the stored values of a
+ *    node keep its mass and momentum up to the rounding of three populations); FP64 and BF16
+ *    storage and LBGK with FP16 storage use the direct form.
  */
 #ifndef LBM_H
 #define LBM_H
