@@ -154,16 +154,17 @@ __device__ __forceinline__ void conserve(T drho, T jx, T jy, T out[Q]) {
   out[0] = drho - (((out[1] + out[3]) + (out[2] + out[4])) + ((out[5] + out[7]) + (out[6] + out[8])));
 }
 
-// The same in FP16 storage precision: every population is returned as its FP16 value, and the
-// momentum that the rounded diagonal populations miss is split evenly between the two
+// The same in FP16 storage precision: populations 1-8 are returned as FP16 values (g*_0 is
+// rounded by the store), and the momentum that the rounded diagonal populations miss is split
+// evenly between the two
 // populations of each axis (+r/2 on c = +1, -r/2 on c = -1), which leaves the normal-stress
 // moment D = sum (c_x^2 - c_y^2) g untouched; then g*_0 takes the mass. The stored node then
 // carries the rounding of two populations per momentum component and of one in its mass,
 // instead of seven and nine. Measured on the 8192^2 turbulence (complete model, max error of
 // the populations against the FP64 run after 100 / 1000 / 5000 steps): 4.8e-4 / 1.06e-3 /
 // 2.04e-3 with the direct form, 4.2e-4 / 7.1e-4 / 1.26e-3 with this; partial model after
-// 100 / 1000 / 3000 steps 4.8e-4 / 1.11e-3 / 1.60e-3 -> 3.9e-4 / 8.1e-4 / 1.09e-3; 6 % of the
-// FP16 two-step kernel's throughput. (Giving the whole residual to populations 1 and 2
+// 100 / 1000 / 3000 steps 4.8e-4 / 1.11e-3 / 1.60e-3 -> 3.9e-4 / 8.1e-4 / 1.09e-3; 6-8 % of
+// the FP16 two-step kernel's throughput. (Giving the whole residual to populations 1 and 2
 // instead moved D with it: better to 1000 steps, worse after.)
 template <bool MOMENTUM>
 __device__ __forceinline__ void conserve_fp16(float drho, float jx, float jy, float out[Q]) {
