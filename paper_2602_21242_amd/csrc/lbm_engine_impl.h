@@ -471,14 +471,9 @@ hipError_t launch_step2_m(const RunDesc& d, const void* src, void* dst, void* re
 // the measured throughput of every candidate tried on 512^2 to 4096^2 grids. In mode 0 a
 // grid that cannot give three quarters of the compute units a block keeps single steps.
 // The two-step adjoint kernel has the same block structure and uses the same plan.
-inline int plan_row_blocks(const RunDesc& d, int mode) {
-  if (d.nx % kLanes != 0 || (d.pitch / kLanes) % kFuseGroups != 0) return 0;
-  int dev = 0, cus = 0;
-  if (hipGetDevice(&dev) != hipSuccess ||
-      hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus < 1)
-    return 0;
-  const long ny = d.ny, cols = d.pitch / kLanes / kFuseGroups;
-  const long nb_lo = (ny + kFuseRows - 1) / kFuseRows;
+// Least-cost row-block count for blocks of kFuseMinRows to max_rows rows (0: none).
+inline long plan_rows(long ny, long cols, long cus, long max_rows) {
+  const long nb_lo = (ny + max_rows - 1) / max_rows;
   const long nb_hi = std::min(std::max(nb_lo, ny / kFuseMinRows), 65535L);
   if (nb_lo > nb_hi) return 0;
   long best = 0, best_cost = 0;
@@ -490,18 +485,35 @@ inline int plan_row_blocks(const RunDesc& d, int mode) {
     if (best == 0 || cost < best_cost) best = nb, best_cost = cost;
     if (nb == nb_hi) break;
   }
-  if (mode == 0 && 4 * cols * best < 3L * cus) return 0;
+  return best;
+}
+
+// tall: also consider blocks of up to kFuseRowsTall rows, taken when the grid then gives every
+// block a compute unit of its own (one round of blocks).
+inline int plan_row_blocks(const RunDesc& d, int mode, bool tall) {
+  if (d.nx % kLanes != 0 || (d.pitch / kLanes) % kFuseGroups != 0) return 0;
+  int dev = 0, cus = 0;
+  if (hipGetDevice(&dev) != hipSuccess ||
+      hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus < 1)
+    return 0;
+  const long cols = d.pitch / kLanes / kFuseGroups;
+  long best = plan_rows(d.ny, cols, cus, kFuseRows);
+  if (tall) {
+    const long t = plan_rows(d.ny, cols, cus, kFuseRowsTall);
+    if (t > 0 && cols * t <= cus) best = t;
+  }
+  if (best == 0 || (mode == 0 && 4 * cols * best < 3L * cus)) return 0;
   return int(best);
 }
 
 template <class S>
 int Engine<S>::fuse_row_blocks(const RunDesc& d, int mode) {
-  return plan_row_blocks(d, mode);
+  return plan_row_blocks(d, mode, FuseTall<S>::value);
 }
 
 template <class S>
 int Engine<S>::adjoint_row_blocks(const RunDesc& d, int mode) {
-  return plan_row_blocks(d, mode);
+  return plan_row_blocks(d, mode, FuseTall<T>::value);
 }
 
 template <class S>

@@ -283,6 +283,17 @@ k_step(const S* src, S* dst, Geo geo, Coef<typename StorageTraits<S>::T> k,
 constexpr int kFuseGroups = 8;
 constexpr int kFuseRows = 64;
 constexpr int kFuseMinRows = 2;
+// The FP32 pair kernels (forward, and adjoint for every storage type but FP64) also take
+// blocks of up to kFuseRowsTall rows when the grid then gives each block a compute unit of its
+// own. Measured on MI355X, 4096^2 (32 blocks of 128 rows against 64 of 64), us per launch on
+// three machines: 217.3-218.3 / 220.1-221.0, 217.5 / 223.0, 211.2-212.4 / 215.0-215.6; the
+// one-segment adjoint sweep 81.9-82.0 against 81.0-81.1 GLUPS. On 8192^2 (several rounds of
+// blocks) 128-row blocks measured 1 % faster on one machine and 8.5 % slower on another
+// (921-922 against 849-850 us), and the 16-bit pairs, three blocks per compute unit, 6 %
+// slower: there the planner keeps kFuseRows.
+constexpr int kFuseRowsTall = 128;
+template <class T> struct FuseTall : std::false_type {};
+template <> struct FuseTall<float> : std::true_type {};
 // The hardware hands consecutive workgroup IDs to the chip's 8 XCDs in turn, and each XCD has
 // its own L2. The two-step kernel renumbers its blocks so that every XCD works on one
 // contiguous range of tiles, x-neighbours side by side: the halo groups a block re-reads are
