@@ -111,3 +111,42 @@ def test_import_rounds_fp64_once(storage):
     assert np.count_nonzero(twice != exp) > g.size // 4  # the inputs do separate the two roundings
     bad = np.argwhere(got != exp)
     assert bad.shape[0] == 0, f"{bad.shape[0]} of {got.size} values differ, e.g. {tuple(bad[0])}"
+
+
+def _moments64(f):
+    """Exact-enough FP64 mass and momentum of one node's nine populations."""
+    cx = np.array([0, 1, 0, -1, 0, 1, -1, -1, 1], dtype=np.float64)
+    cy = np.array([0, 0, 1, 0, -1, 1, 1, -1, -1], dtype=np.float64)
+    return np.sum(f), np.sum(cx * f), np.sum(cy * f)
+
+
+@pytest.mark.parametrize("model", ["complete", "partial", "uc"])
+def test_fp16_collision_keeps_mass_and_momentum_of_stored_values(model):
+    """With FP16 storage the OReg collision's stored populations keep the node's mass and
+    momentum up to the rounding of g*_0 (mass) and of the two axis populations of each
+    direction (momentum), instead of up to the rounding of every population. A spatially
+    uniform state is unchanged by streaming, so one step maps each node's stored populations
+    to its next stored populations: their FP64 moments are compared directly, over many
+    random non-equilibrium states. The uncorrected model keeps only the mass (Sec. 3)."""
+    nx, ny, th = 64, 2, 0.4
+    w = _rest_weights(th)
+    rng = np.random.default_rng(23)
+    eps32 = np.finfo(np.float32).eps
+    for trial in range(24):
+        g = rng.standard_normal(9) * 10.0 ** rng.uniform(-3, -1.3)
+        f = np.broadcast_to((g + w)[:, None, None], (9, ny, nx)).copy()
+        sim = gpu_sim(nx, ny, th, 0.02, model, "f16", "ab", f0=f)
+        f0 = sim.populations().cpu().numpy()
+        sim.step(1)
+        f1 = sim.populations().cpu().numpy()
+        assert np.array_equal(f1, np.broadcast_to(f1[:, :1, :1], f1.shape))  # still uniform
+        a, b = f0[:, 0, 0], f1[:, 0, 0]
+        g1 = b - w
+        assert np.max(np.abs(b - a)) > 0  # the collision changed the state
+        half_ulp = lambda i: 0.5 * float(np.spacing(np.abs(np.float16(g1[i]))))
+        slack = 64 * eps32 * np.max(np.abs(np.concatenate([a - w, g1])))  # FP32 sums
+        (m0, jx0, jy0), (m1, jx1, jy1) = _moments64(a), _moments64(b)
+        assert abs(m1 - m0) <= half_ulp(0) + slack, (trial, m1 - m0)
+        if model != "uc":
+            assert abs(jx1 - jx0) <= half_ulp(1) + half_ulp(3) + slack, (trial, jx1 - jx0)
+            assert abs(jy1 - jy0) <= half_ulp(2) + half_ulp(4) + slack, (trial, jy1 - jy0)
