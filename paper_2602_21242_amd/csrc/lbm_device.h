@@ -132,6 +132,17 @@ struct Coef {
 // Moments recorded per node and step for the adjoint: rho, u_x, u_y, N_xx, N_xy.
 constexpr int NREC = 5;
 
+// a * b + c with one rounding. The collision writes every fused product this way and turns
+// the compiler's own contraction off: which of two products feeding a sum the compiler fuses
+// depends on how many other uses each has, so a kernel that needs only some of the outputs
+// (the two-step kernel's halo columns) rounded the ones it kept differently (LBGK: 20 % of
+// the populations of a 2048 x 130 grid differed after two launches).
+template <class T>
+__device__ __forceinline__ T fmad(T a, T b, T c) {
+  if constexpr (sizeof(T) == 8) return __builtin_fma(a, b, c);
+  else return __builtin_fmaf(a, b, c);
+}
+
 // 1/x: FP32 uses the hardware reciprocal refined by one Newton step (within one ulp of the
 // correctly rounded quotient); FP64 divides.
 template <class T>
@@ -162,23 +173,25 @@ __device__ __forceinline__ void conserve(T drho, T jx, T jy, T out[Q]) {
 // carries the rounding of two populations per momentum component and of one in its mass,
 // instead of seven and nine. Measured on the 8192^2 turbulence (complete model, max error of
 // the populations against the FP64 run after 100 / 1000 / 5000 steps): 4.8e-4 / 1.06e-3 /
-// 2.04e-3 with the direct form, 4.2e-4 / 7.1e-4 / 1.26e-3 with this; partial model after
+// 2.04e-3 with the direct form, 4.2-4.5e-4 / 6.8-7.1e-4 / 1.26-1.27e-3 with this (two
+// arrangements of the collision's fused products); partial model after
 // 100 / 1000 / 3000 steps 4.8e-4 / 1.11e-3 / 1.60e-3 -> 3.9e-4 / 8.1e-4 / 1.09e-3; 6-8 % of
 // the FP16 two-step kernel's throughput. (Giving the whole residual to populations 1 and 2
 // instead moved D with it: better to 1000 steps, worse after.)
 template <bool MOMENTUM>
 __device__ __forceinline__ void conserve_fp16(float drho, float jx, float jy, float out[Q]) {
+#pragma clang fp contract(off)
   auto q = [](float v) { return float(_Float16(v)); };
 #pragma unroll
   for (int i = 5; i < Q; ++i) out[i] = q(out[i]);
   const float d57 = out[5] - out[7], d68 = out[6] - out[8];
   if (MOMENTUM) {
-    const float hrx = 0.5f * (jx - ((out[1] - out[3]) + (d57 - d68)));
-    const float hry = 0.5f * (jy - ((out[2] - out[4]) + (d57 + d68)));
-    out[1] = q(out[1] + hrx);
-    out[3] = q(out[3] - hrx);
-    out[2] = q(out[2] + hry);
-    out[4] = q(out[4] - hry);
+    const float rx = jx - ((out[1] - out[3]) + (d57 - d68));
+    const float ry = jy - ((out[2] - out[4]) + (d57 + d68));
+    out[1] = q(fmad(0.5f, rx, out[1]));
+    out[3] = q(fmad(-0.5f, rx, out[3]));
+    out[2] = q(fmad(0.5f, ry, out[2]));
+    out[4] = q(fmad(-0.5f, ry, out[4]));
   } else {
 #pragma unroll
     for (int i = 1; i < 5; ++i) out[i] = q(out[i]);
@@ -199,7 +212,9 @@ __device__ __forceinline__ void conserve_fp16(float drho, float jx, float jy, fl
 // value of c_x: three FMAs per population. (The longer form P_i (drho + t_i) + E_i + Psi_i,
 // P_i = Phi_x Phi_y, needs about six; with the two-step kernel's buffer accesses the short form
 // measured faster for every storage type on MI355X: FP32 pair 150.1 -> 153.6 GLUPS at 4096^2,
-// 152.2 -> 156.8 at 8192^2, FP64 pair 77.3 -> 78.5.)
+// 152.2 -> 156.8 at 8192^2, FP64 pair 77.3 -> 78.5.) Every fused product is written out with
+// fmad, in the places where the compiler's own contraction had put them, with contraction off,
+// so that the rounding of each output does not depend on which other outputs a caller uses.
 //
 // With CONSERVE = 1 the populations 0, 1 and 2 are then taken from the conservation laws the
 // collision obeys (eq:density-momentum; the corrections keep them, eq:genOReg-constraints):
@@ -218,6 +233,7 @@ __device__ __forceinline__ void conserve_fp16(float drho, float jx, float jy, fl
 // in FP16 storage precision (conserve_fp16) for the OReg models.
 template <class T, int MODEL, int CONSERVE = 0>
 __device__ __forceinline__ void collide(const T g[Q], T out[Q], const Coef<T>& k, T rec[NREC]) {
+#pragma clang fp contract(off)
   // Moments (Sec. 1): rho = rho0 + sum g, j = sum c g, D = sum (cx^2 - cy^2) g, Pxy = sum cx cy g.
   const T s13 = g[1] + g[3], s24 = g[2] + g[4], s57 = g[5] + g[7], s68 = g[6] + g[8];
   const T d57 = g[5] - g[7], d68 = g[6] - g[8];
@@ -231,16 +247,14 @@ __device__ __forceinline__ void collide(const T g[Q], T out[Q], const Coef<T>& k
 
   // Guided equilibrium (eq:guidedEq) as a product of per-axis factors
   // Phi(0,u) = 1 - theta - u^2, Phi(+-1,u) = (theta + u^2 +- u)/2, written as rest value + d.
-  const T hux = T(0.5) * ux, huy = T(0.5) * uy, hux2 = T(0.5) * ux2, huy2 = T(0.5) * uy2;
-  const T dx0 = -ux2, dxp = hux2 + hux, dxm = hux2 - hux;
-  const T dy0 = -uy2, dyp = huy2 + huy, dym = huy2 - huy;
-  const T hx0 = k.r0 + dx0, hxp = k.r1 + dxp, hxm = k.r1 + dxm;
-  const T hy0 = k.r0 + dy0, hyp = k.r1 + dyp, hym = k.r1 + dym;
+  const T hux = T(0.5) * ux, huy = T(0.5) * uy;
+  const T dx0 = -ux2, dxp = fmad(T(0.5), ux2, hux), dxm = fmad(T(0.5), ux2, -hux);
+  const T dy0 = -uy2, dyp = fmad(T(0.5), uy2, huy), dym = fmad(T(0.5), uy2, -huy);
+  const T hx0 = fmad(-ux, ux, k.r0), hxp = k.r1 + dxp, hxm = k.r1 + dxm;
+  const T hy0 = fmad(-uy, uy, k.r0), hyp = k.r1 + dyp, hym = k.r1 + dym;
   // f_i^eq - w_i rho0 = drho P_i + E_i with P_i = Phi_x Phi_y and
   // E_i = rho0 (d_x Phi_y + r_x d_y), free of cancellation against w_i rho0.
   const T rdx0 = k.rho0 * dx0, rdxp = k.rho0 * dxp, rdxm = k.rho0 * dxm;
-  const T a0m = k.rr0 * dym, a00 = k.rr0 * dy0, a0p = k.rr0 * dyp;  // rho0 r_x d_y, c_x = 0
-  const T a1m = k.rr1 * dym, a10 = k.rr1 * dy0, a1p = k.rr1 * dyp;  // rho0 r_x d_y, c_x = +-1
   if (rec) {
     rec[0] = rho;
     rec[1] = ux;
@@ -249,13 +263,15 @@ __device__ __forceinline__ void collide(const T g[Q], T out[Q], const Coef<T>& k
 
   if (MODEL == M_BGK) {
     // f_i^eq - w_i rho0 = Phi_y (Phi_x drho + rho0 d_x) + rho0 r_x d_y
-    const T Km = hxm * drho + rdxm, K0 = hx0 * drho + rdx0, Kp = hxp * drho + rdxp;
+    const T a0m = k.rr0 * dym, a00 = k.rr0 * dy0, a0p = k.rr0 * dyp;  // rho0 r_x d_y, c_x = 0
+    const T a1m = k.rr1 * dym, a10 = k.rr1 * dy0, a1p = k.rr1 * dyp;  // rho0 r_x d_y, c_x = +-1
+    const T Km = fmad(hxm, drho, rdxm), K0 = fmad(hx0, drho, rdx0), Kp = fmad(hxp, drho, rdxp);
 #pragma unroll
     for (int i = 0; i < Q; ++i) {
       const T hy = sel(cy(i), hym, hy0, hyp);
       const T rdy = cx(i) == 0 ? sel(cy(i), a0m, a00, a0p) : sel(cy(i), a1m, a10, a1p);
-      const T feqs = hy * sel(cx(i), Km, K0, Kp) + rdy;
-      out[i] = feqs + k.omb * (g[i] - feqs);
+      const T feqs = fmad(hy, sel(cx(i), Km, K0, Kp), rdy);
+      out[i] = fmad(k.omb, g[i] - feqs, feqs);
     }
     if constexpr (CONSERVE == 1) conserve<T, true>(drho, jx, jy, out);
     if (rec) rec[3] = rec[4] = T(0);
@@ -266,9 +282,9 @@ __device__ __forceinline__ void collide(const T g[Q], T out[Q], const Coef<T>& k
   // N_xy = Pxy - rho ux uy.
   const T Dm = s13 - s24;
   const T Pxy = s57 - s68;
-  const T du2 = ux2 - uy2;
-  const T Nxx = T(0.5) * (Dm - rho * du2);
-  const T Nxy = Pxy - jx * uy;
+  const T du2 = fmad(-uy, uy, ux2);
+  const T Nxx = T(0.5) * fmad(-rho, du2, Dm);
+  const T Nxy = fmad(-jx, uy, Pxy);
   if (rec) {
     rec[3] = Nxx;
     rec[4] = Nxy;
@@ -279,23 +295,23 @@ __device__ __forceinline__ void collide(const T g[Q], T out[Q], const Coef<T>& k
   // all (1 - 1/tau) times the paper's quantities. drho is folded into the x-factor so that
   // P_i (drho + t_i) is one product.
   const T n1 = Nxx * k.omb_inv2th2, n2 = Nxy * (T(2) * k.omb_inv2th2);
-  const T Cxm = T(-1) - ux, Cx0 = -ux, Cxp = T(1) - ux;
-  const T Cym = T(-1) - uy, Cy0 = -uy, Cyp = T(1) - uy;
-  const T X1m = Cxm * Cxm * n1 + drho, X10 = ux2 * n1 + drho, X1p = Cxp * Cxp * n1 + drho;
+  const T Cxm = fmad(-jx, rinv, T(-1)), Cx0 = -ux, Cxp = fmad(-jx, rinv, T(1));
+  const T Cym = fmad(-jy, rinv, T(-1)), Cy0 = -uy, Cyp = fmad(-jy, rinv, T(1));
+  const T X1m = fmad(Cxm * Cxm, n1, drho), X10 = fmad(ux2, n1, drho), X1p = fmad(Cxp * Cxp, n1, drho);
   const T Y1m = Cym * Cym * n1, Y10 = uy2 * n1, Y1p = Cyp * Cyp * n1;
   const T Y2m = Cym * n2, Y20 = Cy0 * n2, Y2p = Cyp * n2;
 
-  T Psi[Q];
+  T Psi[Q];  // -0: rho0 r_x d_y + Psi_i is then a plain product where Psi_i vanishes
 #pragma unroll
-  for (int i = 0; i < Q; ++i) Psi[i] = T(0);
+  for (int i = 0; i < Q; ++i) Psi[i] = T(-0.0);
   if (MODEL == M_PARTIAL || MODEL == M_COMPLETE) {
     // psi = sum_i c_i f_i^OReg (eq:oreg-mom-compatibility) in closed form:
     // psi_x = n1 u_x (1 - 3 theta - u_x^2), psi_y = -n1 u_y (1 - 3 theta - u_y^2).
     // Every Psi_i takes half of a psi or Pi~ component, so halves are formed directly.
-    const T hpsx = n1 * hux * (k.c3 - ux2);
-    const T hpsy = -(n1 * huy * (k.c3 - uy2));
+    const T nhx = n1 * hux, nhy = n1 * huy, cmx = fmad(-ux, ux, k.c3), cmy = fmad(-uy, uy, k.c3);
     if (MODEL == M_PARTIAL) {
       // eq:partial-corrections
+      const T hpsx = nhx * cmx, hpsy = -(nhy * cmy);
       Psi[1] = -hpsx;
       Psi[3] = hpsx;
       Psi[2] = -hpsy;
@@ -304,29 +320,42 @@ __device__ __forceinline__ void collide(const T g[Q], T out[Q], const Coef<T>& k
       // Prefactor (eq:geq-prefactor-evaluation), pf = -(1/(4 theta^2)) sum (cx^2 - cy^2) f^OReg
       // with sum (cx^2 - cy^2) f^OReg = n1 (2 theta (1 - theta) + e_x + e_y),
       // e = u^2 (u^2 - 1), and the stress error's three cases (halved).
-      const T exx = ux2 * (ux2 - T(1)), eyy = uy2 * (uy2 - T(1));
-      const T hpf = -k.inv8th2 * (n1 * (k.b0 + (exx + eyy)));
-      const T hPtxx = -hpf * (k.a0 + exx), hPtyy = hpf * (k.a0 + eyy), hPtxy = hpf * (ux * uy * du2);
+      const T mx = fmad(ux, ux, T(-1)), my = fmad(uy, uy, T(-1)), exx = ux2 * mx;
+      const T hpf = -k.inv8th2 * (n1 * (k.b0 + fmad(uy2, my, exx)));
+      // hPt_xx = -mxx, hPt_yy, hPt_xy (halved stress error); hpsx = nhx cmx, hpsy = -nhy cmy
+      const T txx = fmad(ux2, mx, k.a0), tyy = fmad(uy2, my, k.a0);
+      const T mxx = hpf * txx, hPtyy = hpf * tyy;
+      const T hPtxy = hpf * (ux * uy * du2);
       // eq:complete-corrections
-      Psi[1] = hPtyy - hpsx;
-      Psi[3] = hPtyy + hpsx;
-      Psi[2] = hPtxx - hpsy;
-      Psi[4] = hPtxx + hpsy;
-      const T s = T(-0.5) * (hPtxx + hPtyy);
-      Psi[5] = Psi[7] = s - T(0.5) * hPtxy;
-      Psi[6] = Psi[8] = s + T(0.5) * hPtxy;
+      Psi[1] = fmad(-nhx, cmx, hPtyy);
+      Psi[3] = fmad(nhx, cmx, hPtyy);
+      Psi[2] = fmad(nhy, cmy, -mxx);
+      Psi[4] = -fmad(nhy, cmy, mxx);
+      const T s = T(-0.5) * fmad(hpf, tyy, -mxx);
+      Psi[5] = Psi[7] = fmad(T(-0.5), hPtxy, s);
+      Psi[6] = Psi[8] = fmad(T(0.5), hPtxy, s);
     }
   }
   // g*_i = (f_i^eq - w_i rho0) + (1 - 1/tau)(f_i^OReg + Psi_i)
   //      = Phi_y (K_x + Phi_x (C_x Y2 - Y1)) + (rho0 r_x d_y + Psi_i), with
   // drho + t_i = X1 - Y1 + C_x Y2 and K_x = Phi_x X1 + rho0 d_x per value of c_x.
-  const T Km = hxm * X1m + rdxm, K0 = hx0 * X10 + rdx0, Kp = hxp * X1p + rdxp;
+  // Which product of K_x is fused: measured on MI355X (two-step kernel, us per launch,
+  // interleaved on one machine), rho0 d_x fused is the faster choice for FP32 storage (8192^2:
+  // 838-850 against 936 with Phi_x X1 fused, whose schedule there falls into a slower memory
+  // access pattern; 4096^2 209-211 against 207), Phi_x X1 fused for the others (FP16 8192^2 738
+  // against 763).
+  T Km, K0, Kp;
+  if constexpr (CONSERVE == 1) {
+    Km = fmad(k.rho0, dxm, hxm * X1m), K0 = fmad(k.rho0, dx0, hx0 * X10), Kp = fmad(k.rho0, dxp, hxp * X1p);
+  } else {
+    Km = fmad(hxm, X1m, rdxm), K0 = fmad(hx0, X10, rdx0), Kp = fmad(hxp, X1p, rdxp);
+  }
 #pragma unroll
   for (int i = 0; i < Q; ++i) {
     const T hx = sel(cx(i), hxm, hx0, hxp), hy = sel(cy(i), hym, hy0, hyp);
-    const T rdy = cx(i) == 0 ? sel(cy(i), a0m, a00, a0p) : sel(cy(i), a1m, a10, a1p);
-    const T v = sel(cx(i), Cxm, Cx0, Cxp) * sel(cy(i), Y2m, Y20, Y2p) - sel(cy(i), Y1m, Y10, Y1p);
-    out[i] = hy * (sel(cx(i), Km, K0, Kp) + hx * v) + (rdy + Psi[i]);
+    const T rr = cx(i) == 0 ? k.rr0 : k.rr1, dy = sel(cy(i), dym, dy0, dyp);
+    const T v = fmad(sel(cx(i), Cxm, Cx0, Cxp), sel(cy(i), Y2m, Y20, Y2p), -sel(cy(i), Y1m, Y10, Y1p));
+    out[i] = fmad(hy, fmad(hx, v, sel(cx(i), Km, K0, Kp)), fmad(rr, dy, Psi[i]));
   }
   if constexpr (CONSERVE == 1) conserve<T, MODEL != M_UC>(drho, jx, jy, out);
   if constexpr (CONSERVE == 2) conserve_fp16<MODEL != M_UC>(drho, jx, jy, out);
