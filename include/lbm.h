@@ -34,9 +34,12 @@
  *    outputs use the compute type. Stores round to nearest even. With LBM_F32 storage the
  *    collision takes populations 0, 1 and 2 from mass and momentum conservation (the same
  *    values in exact arithmetic), so FP32 rounding adds no drift of mass or momentum; with
- *    LBM_F16 storage and the OReg models it does so in FP16 precision (the stored values of a
- *    node keep its mass and momentum up to the rounding of three populations); FP64 and BF16
- *    storage and LBGK with FP16 storage use the direct form.
+ *    LBM_F16 storage and the OReg models it does so in FP16 precision: the axis populations
+ *    are rounded to nearest even, the momentum they then miss goes to the four diagonal
+ *    populations in a combination that changes no other moment of second order or lower,
+ *    each diagonal is rounded once with its share, and g*_0 takes the mass (the stored values
+ *    of a node keep its mass up to the rounding of g*_0 and its momentum up to that of the
+ *    four diagonals); FP64 and BF16 storage and LBGK with FP16 storage use the direct form.
  */
 #ifndef LBM_H
 #define LBM_H

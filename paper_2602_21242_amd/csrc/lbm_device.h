@@ -165,36 +165,41 @@ __device__ __forceinline__ void conserve(T drho, T jx, T jy, T out[Q]) {
   out[0] = drho - (((out[1] + out[3]) + (out[2] + out[4])) + ((out[5] + out[7]) + (out[6] + out[8])));
 }
 
-// The same in FP16 storage precision: populations 1-8 are returned as FP16 values (g*_0 is
-// rounded by the store), and the momentum that the rounded diagonal populations miss is split
-// evenly between the two
-// populations of each axis (+r/2 on c = +1, -r/2 on c = -1), which leaves the normal-stress
-// moment D = sum (c_x^2 - c_y^2) g untouched; then g*_0 takes the mass. The stored node then
-// carries the rounding of two populations per momentum component and of one in its mass,
-// instead of seven and nine. Measured on the 8192^2 turbulence (complete model, max error of
-// the populations against the FP64 run after 100 / 1000 / 5000 steps): 4.8e-4 / 1.06e-3 /
-// 2.04e-3 with the direct form, 4.2-4.5e-4 / 6.8-7.1e-4 / 1.26-1.27e-3 with this (two
-// arrangements of the collision's fused products); partial model after
-// 100 / 1000 / 3000 steps 4.8e-4 / 1.11e-3 / 1.60e-3 -> 3.9e-4 / 8.1e-4 / 1.09e-3; 6-8 % of
-// the FP16 two-step kernel's throughput. (Giving the whole residual to populations 1 and 2
-// instead moved D with it: better to 1000 steps, worse after.)
+// The same in FP16 storage precision (OReg models): populations 1-8 are returned as FP16 values
+// (g*_0 is rounded by the store). The axis populations 1-4 are rounded first; the momentum
+// (r_x, r_y) they then miss goes to the four diagonal populations, (r_x + r_y)/4 to 5,
+// -(r_x + r_y)/4 to 7, (r_x - r_y)/4 to 8 and -(r_x - r_y)/4 to 6, a combination that carries
+// exactly that momentum and leaves the mass, the normal-stress difference D and the shear
+// moment P_xy untouched; each diagonal is rounded once with its share (one fused multiply-add
+// into FP16), and g*_0 takes the mass. The stored node's momentum then carries the rounding of
+// the four diagonal populations, whose values are the node's smallest (equilibrium weight
+// theta^2/4 against theta (1 - theta)/2 on the axes), and its mass that of g*_0, instead of
+// seven and nine roundings. Measured on the 8192^2 turbulence (complete model, max error of the
+// populations against the FP64 run after 100 / 1000 / 2000 / 3000 / 5000 steps): direct form
+// 4.8e-4 / 1.06e-3 / - / - / 2.04e-3; diagonals rounded first and the residual split over each
+// axis' pair 4.5e-4 / 6.8e-4 / 9.4e-4 / 1.08e-3 / 1.27e-3; this 3.4e-4 / 3.9e-4 / 4.3e-4 /
+// 4.7e-4 / 5.3e-4, in the same time per launch as the axis-pair split (737 us per 8192^2
+// two-step launch, interleaved on one machine). Not for LBGK, which keeps every
+// non-equilibrium moment and whose error is not carried by the momentum: with this its error
+// after 5000 steps rose from 3.3e-3 to 3.7e-3, at 9 % of its throughput.
 template <bool MOMENTUM>
 __device__ __forceinline__ void conserve_fp16(float drho, float jx, float jy, float out[Q]) {
 #pragma clang fp contract(off)
   auto q = [](float v) { return float(_Float16(v)); };
-#pragma unroll
-  for (int i = 5; i < Q; ++i) out[i] = q(out[i]);
-  const float d57 = out[5] - out[7], d68 = out[6] - out[8];
   if (MOMENTUM) {
-    const float rx = jx - ((out[1] - out[3]) + (d57 - d68));
-    const float ry = jy - ((out[2] - out[4]) + (d57 + d68));
-    out[1] = q(fmad(0.5f, rx, out[1]));
-    out[3] = q(fmad(-0.5f, rx, out[3]));
-    out[2] = q(fmad(0.5f, ry, out[2]));
-    out[4] = q(fmad(-0.5f, ry, out[4]));
-  } else {
 #pragma unroll
     for (int i = 1; i < 5; ++i) out[i] = q(out[i]);
+    const float d57 = out[5] - out[7], d68 = out[6] - out[8];
+    const float rx = jx - ((out[1] - out[3]) + (d57 - d68));
+    const float ry = jy - ((out[2] - out[4]) + (d57 + d68));
+    const float sp = rx + ry, sm = rx - ry;
+    out[5] = q(fmad(0.25f, sp, out[5]));
+    out[7] = q(fmad(-0.25f, sp, out[7]));
+    out[8] = q(fmad(0.25f, sm, out[8]));
+    out[6] = q(fmad(-0.25f, sm, out[6]));
+  } else {
+#pragma unroll
+    for (int i = 1; i < Q; ++i) out[i] = q(out[i]);
   }
   out[0] = drho - (((out[1] + out[3]) + (out[2] + out[4])) + ((out[5] + out[7]) + (out[6] + out[8])));
 }
