@@ -399,14 +399,13 @@ __device__ __forceinline__ void collide_vjp(const T fbs[Q], const T rec[NREC], c
     for (int a = 0; a < 3; ++a) out[a] = M[a][0] * v[0] + M[a][1] * v[1] + M[a][2] * v[2];
   };
   auto dot = [](const T x[3], const T y[3]) { return x[0] * y[0] + x[1] * y[1] + x[2] * y[2]; };
+  // Terms whose coefficient is a lattice constant of 0 are left out (a product with a zero
+  // constant stays in the code, since 0 * x is NaN for infinite x: 29 of the 365 vector
+  // instructions of the FP32 complete model), the others are summed in the order of the full
+  // sums, so that the results do not change.
 
-  T uxb = T(0), uyb = T(0), Nxxb = T(0), Nxyb = T(0);
-  T direct_scale = T(0);  // LBGK: fbar gets omb fbs directly
-  T eq_scale = T(1);      // weight of fbs in the equilibrium part
-  if (MODEL == M_BGK) {
-    direct_scale = k.omb;
-    eq_scale = T(1) - k.omb;
-  } else {
+  T uxb, uyb;
+  if (MODEL != M_BGK) {
     // Weights of the OReg population f^OReg_i = P_i t_i in the output: omb fbs, plus, for the
     // corrected models, the chain through Psi, which depends on f^OReg via psi = sum c f^OReg
     // and (complete model) the prefactor, a moment of f^OReg.
@@ -415,6 +414,7 @@ __device__ __forceinline__ void collide_vjp(const T fbs[Q], const T rec[NREC], c
     for (int a = 0; a < 3; ++a)
 #pragma unroll
       for (int b = 0; b < 3; ++b) W[a][b] = k.omb * F[a][b];
+    T uxc, uyc;  // the complete model's direct u-dependence of the stress error
     if (MODEL == M_PARTIAL || MODEL == M_COMPLETE) {
       // Psi bar = omb fbs; psi bar_x = (Psib_3 - Psib_1)/2, psi bar_y = (Psib_4 - Psib_2)/2.
       const T psxb = T(0.5) * (W[0][1] - W[2][1]);
@@ -432,18 +432,23 @@ __device__ __forceinline__ void collide_vjp(const T fbs[Q], const T rec[NREC], c
         const T Ptxyb = T(0.25) * ((W[0][2] + W[2][0]) - (W[2][2] + W[0][0]));
         const T pfb = -Ptxxb * ax + Ptyyb * ay + Ptxyb * bxy;
         const T axb = -Ptxxb * pf, ayb = Ptyyb * pf, bb = Ptxyb * pf;
-        uxb += axb * (T(4) * ux2 - T(2)) * ux + bb * uy * (T(3) * ux2 - uy2);
-        uyb += ayb * (T(4) * uy2 - T(2)) * uy + bb * ux * (ux2 - T(3) * uy2);
+        uxc = axb * (T(4) * ux2 - T(2)) * ux + bb * uy * (T(3) * ux2 - uy2);
+        uyc = ayb * (T(4) * uy2 - T(2)) * uy + bb * ux * (ux2 - T(3) * uy2);
         const T q = k.inv4th2 * pfb;
         W[2][1] -= q;  // populations 1 and 3
         W[0][1] -= q;
         W[1][2] += q;  // populations 2 and 4
         W[1][0] += q;
       }
-#pragma unroll
-      for (int a = 0; a < 3; ++a)
-#pragma unroll
-        for (int b = 0; b < 3; ++b) W[a][b] += T(a - 1) * psxb + T(b - 1) * psyb;
+      // W_ab += c_a psi bar_x + c_b psi bar_y with c = a - 1 (edges one term, corners the sum).
+      W[2][1] += psxb;
+      W[0][1] += -psxb;
+      W[1][2] += psyb;
+      W[1][0] += -psyb;
+      W[2][2] += psxb + psyb;
+      W[0][0] += -psxb - psyb;
+      W[2][0] += psxb - psyb;
+      W[0][2] += -psxb + psyb;
     }
     // f^OReg_ab = [(A2_a B0_b - A0_a B2_b) N_xx + 2 A1_a B1_b N_xy] / (2 theta^2).
     const T Cx[3] = {T(-1) - ux, -ux, T(1) - ux};
@@ -469,31 +474,64 @@ __device__ __forceinline__ void collide_vjp(const T fbs[Q], const T rec[NREC], c
     matvec(W, dB1, WdB1);
     matvec(W, dB2, WdB2);
     const T kx = Nxx * k.inv2th2, ky = Nxy * (T(2) * k.inv2th2);
-    Nxxb = k.inv2th2 * (dot(A2, WB0) - dot(A0, WB2));
-    Nxyb = (T(2) * k.inv2th2) * dot(A1, WB1);
-    uxb += kx * (dot(dA2, WB0) - dot(dA0, WB2)) + ky * dot(dA1, WB1);
-    uyb += kx * (dot(A2, WdB0) - dot(A0, WdB2)) + ky * dot(A1, WdB1);
-  }
-  // Equilibrium part rho A0_a B0_b (shifted by a constant).
-  T FB0[3], FdB0[3];
-  matvec(F, B0, FB0);
-  matvec(F, dB0, FdB0);
-  T rhob = eq_scale * dot(A0, FB0);
-  uxb += eq_scale * rho * dot(dA0, FB0);
-  uyb += eq_scale * rho * dot(A0, FdB0);
-  // Chain (rho, u, N) -> (rho, j, D, Pxy).
-  const T Db = T(0.5) * Nxxb;
-  const T Pxyb = Nxyb;
-  rhob += T(-0.5) * Nxxb * (ux2 - uy2) - Nxyb * ux * uy;
-  uxb += -Nxxb * rho * ux - Nxyb * rho * uy;
-  uyb += Nxxb * rho * uy - Nxyb * rho * ux;
-  const T rinv = recip(rho);
-  const T jxb = uxb * rinv, jyb = uyb * rinv;
-  rhob -= (uxb * ux + uyb * uy) * rinv;
+    const T Nxxb = k.inv2th2 * (dot(A2, WB0) - dot(A0, WB2));
+    const T Nxyb = (T(2) * k.inv2th2) * dot(A1, WB1);
+    const T uxo = kx * (dot(dA2, WB0) - dot(dA0, WB2)) + ky * dot(dA1, WB1);
+    const T uyo = kx * (dot(A2, WdB0) - dot(A0, WdB2)) + ky * dot(A1, WdB1);
+    if (MODEL == M_COMPLETE) {
+      uxb = uxc + uxo;
+      uyb = uyc + uyo;
+    } else {
+      uxb = uxo;
+      uyb = uyo;
+    }
+    const T Db = T(0.5) * Nxxb;
+    const T Pxyb = Nxyb;
+    // Equilibrium part rho A0_a B0_b (shifted by a constant).
+    T FB0[3], FdB0[3];
+    matvec(F, B0, FB0);
+    matvec(F, dB0, FdB0);
+    T rhob = dot(A0, FB0);
+    uxb += rho * dot(dA0, FB0);
+    uyb += rho * dot(A0, FdB0);
+    // Chain (rho, u, N) -> (rho, j, D, Pxy).
+    rhob += T(-0.5) * Nxxb * (ux2 - uy2) - Nxyb * ux * uy;
+    uxb += -Nxxb * rho * ux - Nxyb * rho * uy;
+    uyb += Nxxb * rho * uy - Nxyb * rho * ux;
+    const T rinv = recip(rho);
+    const T jxb = uxb * rinv, jyb = uyb * rinv;
+    rhob -= (uxb * ux + uyb * uy) * rinv;
+    // fbar_i = rhob + c_ix jxb + c_iy jyb + (c_ix^2 - c_iy^2) Db + c_ix c_iy Pxyb, nonzero
+    // terms in this order.
 #pragma unroll
-  for (int i = 0; i < Q; ++i)
-    fbar[i] = direct_scale * fbs[i] + rhob + T(cx(i)) * jxb + T(cy(i)) * jyb + T(cx(i) * cx(i) - cy(i) * cy(i)) * Db +
-              T(cx(i) * cy(i)) * Pxyb;
+    for (int i = 0; i < Q; ++i) {
+      T t = rhob;
+      if (cx(i) != 0) t = t + (cx(i) > 0 ? jxb : -jxb);
+      if (cy(i) != 0) t = t + (cy(i) > 0 ? jyb : -jyb);
+      if (cx(i) * cx(i) != cy(i) * cy(i)) t = t + (cx(i) * cx(i) > cy(i) * cy(i) ? Db : -Db);
+      if (cx(i) * cy(i) != 0) t = t + (cx(i) * cy(i) > 0 ? Pxyb : -Pxyb);
+      fbar[i] = t;
+    }
+  } else {
+    // LBGK: the equilibrium part rho A0_a B0_b weighted 1 - omb, and omb fbs directly.
+    const T es = T(1) - k.omb;
+    T FB0[3], FdB0[3];
+    matvec(F, B0, FB0);
+    matvec(F, dB0, FdB0);
+    T rhob = es * dot(A0, FB0);
+    uxb = es * rho * dot(dA0, FB0);
+    uyb = es * rho * dot(A0, FdB0);
+    const T rinv = recip(rho);
+    const T jxb = uxb * rinv, jyb = uyb * rinv;
+    rhob -= (uxb * ux + uyb * uy) * rinv;
+#pragma unroll
+    for (int i = 0; i < Q; ++i) {
+      T t = fmad(k.omb, fbs[i], rhob);
+      if (cx(i) != 0) t = t + (cx(i) > 0 ? jxb : -jxb);
+      if (cy(i) != 0) t = t + (cy(i) > 0 ? jyb : -jyb);
+      fbar[i] = t;
+    }
+  }
 }
 
 }  // namespace lbm
