@@ -235,8 +235,8 @@ k_step(const S* src, S* dst, Geo geo, Coef<typename StorageTraits<S>::T> k,
   const size_t rsb = size_t(geo.rs) * sizeof(S), psb = size_t(geo.ps) * sizeof(S);
   const char* sr[3] = {reinterpret_cast<const char*>(src) + ym * rsb, reinterpret_cast<const char*>(src) + y * rsb,
                        reinterpret_cast<const char*>(src) + yp * rsb};
-  char* dr[3] = {reinterpret_cast<char*>(dst) + ym * rsb, reinterpret_cast<char*>(dst) + y * rsb,
-                 reinterpret_cast<char*>(dst) + yp * rsb};
+  // Stores through buffer descriptors of the three rows (cache policy kAuxStore).
+  const RowRes dr[3] = {row_res(dst, rsb, ym), row_res(dst, rsb, y), row_res(dst, rsb, yp)};
 
   typename Tr::Raw gs[NPT][Q];
 #pragma unroll
@@ -258,9 +258,9 @@ k_step(const S* src, S* dst, Geo geo, Coef<typename StorageTraits<S>::T> k,
     for (int i = 0; i < Q; ++i) g[i] = Tr::load_raw(gs[n][i]);
     collide<T, MODEL, ConserveMode<S>::value>(g, out, k, REC ? rv : nullptr);
     if constexpr (REC) {
-      char* rrow = reinterpret_cast<char*>(rec) + y * (size_t(rec_rs) * sizeof(T));
+      const RowRes rr = row_res(rec, size_t(rec_rs) * sizeof(T), y);
 #pragma unroll
-      for (int r = 0; r < NREC; ++r) st1(at<T>(rrow + r * size_t(geo.ps) * sizeof(T), rp[n].p0), rv[r]);
+      for (int r = 0; r < NREC; ++r) stb<T>(rr, r * geo.ps * int(sizeof(T)), uint32_t(rp[n].p0) * uint32_t(sizeof(T)), rv[r]);
     }
     static_for<0, Q>([&](auto I) {
       constexpr int i = decltype(I)::value;
@@ -268,7 +268,7 @@ k_step(const S* src, S* dst, Geo geo, Coef<typename StorageTraits<S>::T> k,
       constexpr int slot = (PH == PH_AA_EVEN) ? opp(i) : i;
       constexpr int dx = shift ? cx(i) : 0;
       constexpr int dy = shift ? cy(i) : 0;
-      st1(at<S>(dr[dy + 1] + slot * psb, rp[n].template of<dx>()), Tr::store(out[i]));
+      stb<S>(dr[dy + 1], slot * int(psb), uint32_t(rp[n].template of<dx>()) * uint32_t(sizeof(S)), Tr::store(out[i]));
     });
   }
 }
