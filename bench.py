@@ -73,6 +73,26 @@ def load_traffic(workload, model, storage, pattern):
     return None if ent is None else ent.get("hbm_bytes_per_launch")
 
 
+def section(var, name, fn):
+    """Run one optional section of the benchmark and merge its dict into `var`. An exception
+    (for instance a device allocation that does not fit next to another process's memory) is
+    recorded under "<name>_error" and the run goes on, so that the headline line is still
+    printed; device memory cached by torch is released either way."""
+    try:
+        var.update(fn())
+    except Exception as e:  # noqa: BLE001 - recorded in the output, not hidden
+        log(f"[bench] {name} failed: {e!r}")
+        var[f"{name}_error"] = repr(e)
+    finally:
+        try:
+            import torch
+            if torch.cuda.is_available():
+                torch.cuda.synchronize()
+                torch.cuda.empty_cache()
+        except Exception:  # noqa: BLE001
+            pass
+
+
 def make_sim(w, model, storage, pattern, fields, **kw):
     import torch
     from paper_2602_21242_amd import Simulation
@@ -331,60 +351,73 @@ def main():
     if not args.quick:
         var = {}
         log("[bench] copy bandwidth")
-        var["d2d_copy_GBs"] = copy_bandwidth()
+        section(var, "d2d_copy", lambda: {"d2d_copy_GBs": copy_bandwidth()})
         steps_v = max(100, min(args.steps, 500))
-        for model, pattern in (("complete", "ab"), ("complete", "aa"), ("bgk", "ab"), ("bgk", "aa"),
-                               ("uc", "aa"), ("partial", "aa")):
-            log(f"[bench] variant tg4096 {model} f32 {pattern}")
-            s = make_sim(w, model, "f32", pattern, fields)
-            sp = s.steps_per_launch
-            m = time_steady(s, steps_v)
-            var[f"tg4096/{model}/f32/{pattern}"] = {"ms_per_step": m, "GLUPS": nodes / (m * 1e-3) / 1e9,
-                                                    "steps_per_launch": sp,
-                                                    "hbm_frac_per_update": 72 * nodes / (m * 1e-3) / 1e9 / HBM_PEAK_GBS}
-            del s
-        # The single-step kernel on the headline workload (one lbm_step(1) call per step).
-        log("[bench] variant tg4096 complete f32 ab, one step per launch")
-        s = make_sim(w, "complete", "f32", "ab", fields)
-        m = time_single_steps(s, steps_v, 0, spin=s, spin_s=0.2)
-        var["tg4096/complete/f32/ab/single-step-kernel"] = {
-            "ms_per_step": m, "GLUPS": nodes / (m * 1e-3) / 1e9, "steps_per_launch": 1,
-            "hbm_frac_per_update": 72 * nodes / (m * 1e-3) / 1e9 / HBM_PEAK_GBS}
-        del s
+
+        def tg4096_variants():
+            res = {}
+            for model, pattern in (("complete", "ab"), ("complete", "aa"), ("bgk", "ab"), ("bgk", "aa"),
+                                   ("uc", "aa"), ("partial", "aa")):
+                log(f"[bench] variant tg4096 {model} f32 {pattern}")
+                s = make_sim(w, model, "f32", pattern, fields)
+                sp = s.steps_per_launch
+                m = time_steady(s, steps_v)
+                res[f"tg4096/{model}/f32/{pattern}"] = {
+                    "ms_per_step": m, "GLUPS": nodes / (m * 1e-3) / 1e9, "steps_per_launch": sp,
+                    "hbm_frac_per_update": 72 * nodes / (m * 1e-3) / 1e9 / HBM_PEAK_GBS}
+                del s
+            # The single-step kernel on the headline workload (one lbm_step(1) call per step).
+            log("[bench] variant tg4096 complete f32 ab, one step per launch")
+            s = make_sim(w, "complete", "f32", "ab", fields)
+            m = time_single_steps(s, steps_v, 0, spin=s, spin_s=0.2)
+            res["tg4096/complete/f32/ab/single-step-kernel"] = {
+                "ms_per_step": m, "GLUPS": nodes / (m * 1e-3) / 1e9, "steps_per_launch": 1,
+                "hbm_frac_per_update": 72 * nodes / (m * 1e-3) / 1e9 / HBM_PEAK_GBS}
+            return res
+
+        section(var, "tg4096_variants", tg4096_variants)
         del fields
+
         # Storage types on the 8192^2 turbulence workload: throughput, and the error table against
         # the FP64 run after 100, 1000 and 5000 steps.
-        wt = inp.WORKLOADS["turb8192"]
-        log("[bench] generating turb8192 fields")
-        tf = wt.fields(seed=0)
-        nt = wt.nx * wt.ny
-        for storage in ("f64", "f32", "f16", "bf16"):
-            log(f"[bench] variant turb8192 complete {storage} ab")
-            s = make_sim(wt, "complete", storage, "ab", tf)
-            sp = s.steps_per_launch
-            m = time_steady(s, 200)
-            ent = {"ms_per_step": m, "GLUPS": nt / (m * 1e-3) / 1e9, "steps_per_launch": sp,
-                   "hbm_frac_per_update": ALG_BYTES[storage] * nt / (m * 1e-3) / 1e9 / HBM_PEAK_GBS}
-            if sp == 2:
-                ent["pair_floor_frac"] = ALG_BYTES[storage] * nt / (sp * m * 1e-3) / 1e9 / HBM_PEAK_GBS
-            del s
-            var[f"turb8192/complete/{storage}/ab"] = ent
-        del tf
+        def turb8192_storage():
+            res = {}
+            wt = inp.WORKLOADS["turb8192"]
+            log("[bench] generating turb8192 fields")
+            tf = wt.fields(seed=0)
+            nt = wt.nx * wt.ny
+            for storage in ("f64", "f32", "f16", "bf16"):
+                log(f"[bench] variant turb8192 complete {storage} ab")
+                s = make_sim(wt, "complete", storage, "ab", tf)
+                sp = s.steps_per_launch
+                m = time_steady(s, 200)
+                ent = {"ms_per_step": m, "GLUPS": nt / (m * 1e-3) / 1e9, "steps_per_launch": sp,
+                       "hbm_frac_per_update": ALG_BYTES[storage] * nt / (m * 1e-3) / 1e9 / HBM_PEAK_GBS}
+                if sp == 2:
+                    ent["pair_floor_frac"] = ALG_BYTES[storage] * nt / (sp * m * 1e-3) / 1e9 / HBM_PEAK_GBS
+                del s
+                res[f"turb8192/complete/{storage}/ab"] = ent
+            return res
+
+        section(var, "turb8192_storage", turb8192_storage)
         if args.precision_steps:
             log("[bench] storage precision on turb8192")
-            var["precision_turb8192"] = bench_precision(inp, checkpoints=(100, 1000, args.precision_steps))
+            section(var, "precision_turb8192", lambda: {
+                "precision_turb8192": bench_precision(inp, checkpoints=(100, 1000, args.precision_steps))})
         # Adjoint: the adjoint kernels at 4096^2 (HBM-sized), the end-to-end gradient on the
         # 1024^2 advected shear wave (500 steps, sqrt(N) checkpoints) and on the 16384 x 4096
         # double shear layer (3000 steps, enstrophy gradient).
         log("[bench] adjoint")
-        var.update(bench_adjoint(inp))
+        section(var, "adjoint", lambda: bench_adjoint(inp))
         if not args.no_dsl:
             log("[bench] double shear layer gradient")
-            var.update(bench_gradient_dsl(inp))
+            section(var, "gradient_dsl16384", lambda: bench_gradient_dsl(inp))
         out["variants"] = var
         if not args.no_cpu:
             log("[bench] CPU oracle baseline")
-            out["cpu_baseline"] = cpu_baseline(w, args.model)
+            cpu = {}
+            section(cpu, "cpu_baseline", lambda: {"cpu_baseline": cpu_baseline(w, args.model)})
+            out.update(cpu)
     out["kernel_source_hash"] = kernel_source_hash()
     print(json.dumps(out), flush=True)
 

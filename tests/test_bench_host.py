@@ -56,3 +56,16 @@ def test_traffic_lookup(tmp_path, monkeypatch):
     assert bench.load_traffic("tg4096", "complete", "f32", "no-such-pattern") is None
     monkeypatch.setattr(bench, "kernel_source_hash", lambda: "0" * 16)
     assert bench.load_traffic("tg4096", "complete", "f32", "ab") is None
+
+
+def test_section_merges_results_and_records_failures():
+    var = {"kept": 1}
+    bench.section(var, "ok", lambda: {"a": 2.0})
+    assert var == {"kept": 1, "a": 2.0}
+
+    def boom():
+        raise RuntimeError("device allocation failed")
+
+    bench.section(var, "big", boom)
+    assert var["kept"] == 1 and var["a"] == 2.0
+    assert "device allocation failed" in var["big_error"]
