@@ -468,6 +468,7 @@ lbm_status lbm_init(const lbm_params* p, void* d_workspace, size_t workspace_byt
     d.tau = p->nu / p->theta + 0.5;  // nu = theta (tau - 1/2)
     d.model = p->model;
     d.walls = p->walls;
+    d.wt_stores = int64_t(lbm::Q) * d.pitch * d.ny * int64_t(storage_size(p->storage)) >= lbm::kWriteThroughBytes;
     d.fuse_rb = (p->pattern == LBM_AB && p->two_step >= 0 && !p->walls)
                     ? dispatch_int(p->storage, [&](auto eng) { return decltype(eng)::fuse_row_blocks(d, p->two_step); })
                     : 0;

@@ -23,7 +23,13 @@ struct RunDesc {
   int fuse_rb;       // row blocks of the two-step kernel; 0: one step per launch
   int adj_rb;        // row blocks of the two-step adjoint kernel; 0: one reverse step per launch
   int walls;         // 1: solid bounce-back columns at x = 0 and x = nx - 1 (A-B only)
+  int wt_stores;     // 1: the step kernels' stores carry the SC1 scope bit (population buffers
+                     // larger than the last-level cache; see kAuxStore)
 };
+
+// Population-buffer size from which the step kernels' stores are written through (SC1): the
+// read and the written buffer of an A-B step then no longer fit the 256 MB last-level cache.
+constexpr int64_t kWriteThroughBytes = int64_t(128) << 20;
 
 // State layout at a given time: f_i(x) = buf[swap ? opp(i) : i][x - shift c_i].
 struct LayoutSel {

@@ -375,8 +375,8 @@ k_ic_adjoint(const S* buf0, RunDesc d, LayoutSel L, const T* fbar, T* uxb, T* uy
 
 // --- step dispatch ---------------------------------------------------------------------------
 
-template <class S, int MODEL, int NPT>
-hipError_t launch_step_n(const RunDesc& d, int phase, const void* src, void* dst, void* rec, hipStream_t st) {
+template <class S, int MODEL, int NPT, bool WT>
+hipError_t launch_step_w(const RunDesc& d, int phase, const void* src, void* dst, void* rec, hipStream_t st) {
   using T = typename StorageTraits<S>::T;
   const Geo g = make_geo(d, NPT);
   const Coef<T> k = make_coef<T>(d);
@@ -385,15 +385,21 @@ hipError_t launch_step_n(const RunDesc& d, int phase, const void* src, void* dst
   T* r = static_cast<T*>(rec);
   const dim3 grid = step_grid(g), block(kBlock);
   if (rec) {
-    if (phase == PH_AB) hipLaunchKernelGGL((k_step<S, MODEL, PH_AB, true, NPT>), grid, block, 0, st, s, o, g, k, r, d.rs_rec);
-    else if (phase == PH_AA_EVEN) hipLaunchKernelGGL((k_step<S, MODEL, PH_AA_EVEN, true, NPT>), grid, block, 0, st, s, o, g, k, r, d.rs_rec);
-    else hipLaunchKernelGGL((k_step<S, MODEL, PH_AA_ODD, true, NPT>), grid, block, 0, st, s, o, g, k, r, d.rs_rec);
+    if (phase == PH_AB) hipLaunchKernelGGL((k_step<S, MODEL, PH_AB, true, NPT, WT>), grid, block, 0, st, s, o, g, k, r, d.rs_rec);
+    else if (phase == PH_AA_EVEN) hipLaunchKernelGGL((k_step<S, MODEL, PH_AA_EVEN, true, NPT, WT>), grid, block, 0, st, s, o, g, k, r, d.rs_rec);
+    else hipLaunchKernelGGL((k_step<S, MODEL, PH_AA_ODD, true, NPT, WT>), grid, block, 0, st, s, o, g, k, r, d.rs_rec);
   } else {
-    if (phase == PH_AB) hipLaunchKernelGGL((k_step<S, MODEL, PH_AB, false, NPT>), grid, block, 0, st, s, o, g, k, r, d.rs_rec);
-    else if (phase == PH_AA_EVEN) hipLaunchKernelGGL((k_step<S, MODEL, PH_AA_EVEN, false, NPT>), grid, block, 0, st, s, o, g, k, r, d.rs_rec);
-    else hipLaunchKernelGGL((k_step<S, MODEL, PH_AA_ODD, false, NPT>), grid, block, 0, st, s, o, g, k, r, d.rs_rec);
+    if (phase == PH_AB) hipLaunchKernelGGL((k_step<S, MODEL, PH_AB, false, NPT, WT>), grid, block, 0, st, s, o, g, k, r, d.rs_rec);
+    else if (phase == PH_AA_EVEN) hipLaunchKernelGGL((k_step<S, MODEL, PH_AA_EVEN, false, NPT, WT>), grid, block, 0, st, s, o, g, k, r, d.rs_rec);
+    else hipLaunchKernelGGL((k_step<S, MODEL, PH_AA_ODD, false, NPT, WT>), grid, block, 0, st, s, o, g, k, r, d.rs_rec);
   }
   return hipGetLastError();
+}
+
+template <class S, int MODEL, int NPT>
+hipError_t launch_step_n(const RunDesc& d, int phase, const void* src, void* dst, void* rec, hipStream_t st) {
+  return d.wt_stores ? launch_step_w<S, MODEL, NPT, true>(d, phase, src, dst, rec, st)
+                     : launch_step_w<S, MODEL, NPT, false>(d, phase, src, dst, rec, st);
 }
 
 // Nodes per thread of the step kernel. Two or four nodes per thread put more loads in flight
@@ -455,10 +461,13 @@ hipError_t launch_step2_m(const RunDesc& d, const void* src, void* dst, void* re
   S* o = static_cast<S*>(dst);
   T* r1 = static_cast<T*>(rec1);
   T* r2 = static_cast<T*>(rec2);
-  if (rec1 && rec2)
-    hipLaunchKernelGGL((k_step2<S, MODEL, true>), grid, block, 0, st, s, o, g, k, r1, r2, d.rs_rec);
-  else
-    hipLaunchKernelGGL((k_step2<S, MODEL, false>), grid, block, 0, st, s, o, g, k, r1, r2, d.rs_rec);
+  if (rec1 && rec2) {
+    if (d.wt_stores) hipLaunchKernelGGL((k_step2<S, MODEL, true, true>), grid, block, 0, st, s, o, g, k, r1, r2, d.rs_rec);
+    else hipLaunchKernelGGL((k_step2<S, MODEL, true, false>), grid, block, 0, st, s, o, g, k, r1, r2, d.rs_rec);
+  } else {
+    if (d.wt_stores) hipLaunchKernelGGL((k_step2<S, MODEL, false, true>), grid, block, 0, st, s, o, g, k, r1, r2, d.rs_rec);
+    else hipLaunchKernelGGL((k_step2<S, MODEL, false, false>), grid, block, 0, st, s, o, g, k, r1, r2, d.rs_rec);
+  }
   return hipGetLastError();
 }
 

@@ -127,13 +127,17 @@ __device__ __forceinline__ S* at(char* base, int p) {
 // lbm_init rejects wider rows.
 constexpr int kRsrcWord3 = 0x00020000;  // resource word 3 of a raw buffer on the gfx9 family
 constexpr int kAuxNT = 2;                // cache-policy operand of a nontemporal access (gfx950)
-// Stores of the buffer-addressed kernels: nontemporal with the SC1 scope bit (device scope,
-// written through rather than held in the XCD's L2). Measured on the FP32 two-step kernel,
-// interleaved on one machine, us per launch: 210.5 -> 206.2 (4096^2), 832.0 -> 826.5 (8192^2);
-// on another 212.3 -> 210.4 and 851.3 -> 841.8. SC1 without the nontemporal bit measured 3.5 %
-// slower than plain nontemporal stores, stores without either hint 10 % slower, SC0 added
-// to either no different; loads with SC1 no faster.
-constexpr int kAuxStore = kAuxNT | 16;
+// Stores of the step kernels on grids whose population buffers exceed the last-level cache
+// (WT, chosen by the host): nontemporal with the SC1 scope bit (device scope, written through
+// rather than held in the XCD's L2). Measured on the FP32 two-step kernel, interleaved on one
+// machine, us per launch: 210.5 -> 206.2 (4096^2), 832.0 -> 826.5 (8192^2); on another
+// 212.3 -> 210.4 and 851.3 -> 841.8; the single-step kernel 186.8 -> 183.5 (4096^2). SC1
+// without the nontemporal bit measured 3.5 % slower than plain nontemporal stores, stores
+// without either hint 10 % slower, SC0 added to either no different; loads with SC1 no faster.
+// On cache-resident grids SC1 costs instead: 1024^2 (38 MB per buffer) pair 18.1 -> 18.7 us,
+// single step 14.2 -> 14.7, AA 13.4 -> 13.8, so there the stores stay plain nontemporal.
+constexpr int kAuxStoreWT = kAuxNT | 16;
+template <bool WT> constexpr int kAuxStore = WT ? kAuxStoreWT : kAuxNT;
 
 struct RowRes {
   __amdgpu_buffer_rsrc_t r;
@@ -163,16 +167,16 @@ __device__ __forceinline__ auto ldb(const RowRes& rr, int soff, uint32_t voff) {
 }
 
 // Store of one element, nontemporal (every kernel writes each location once per launch), with
-// the cache policy kAuxStore.
-template <class E>
+// the cache policy AUX.
+template <class E, int AUX>
 __device__ __forceinline__ void stb(const RowRes& rr, int soff, uint32_t voff, E v) {
   if constexpr (sizeof(E) == 8) {
     using V2 = unsigned int __attribute__((ext_vector_type(2)));
-    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(V2, v), rr.r, int(voff), soff, kAuxStore);
+    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(V2, v), rr.r, int(voff), soff, AUX);
   } else if constexpr (sizeof(E) == 4) {
-    __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(uint32_t, v), rr.r, int(voff), soff, kAuxStore);
+    __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(uint32_t, v), rr.r, int(voff), soff, AUX);
   } else {
-    __builtin_amdgcn_raw_buffer_store_b16(__builtin_bit_cast(uint16_t, v), rr.r, int(voff), soff, kAuxStore);
+    __builtin_amdgcn_raw_buffer_store_b16(__builtin_bit_cast(uint16_t, v), rr.r, int(voff), soff, AUX);
   }
 }
 
@@ -212,7 +216,7 @@ __device__ __forceinline__ int first_group(int& y, int& lane) {
 // per wavefront. src and dst alias in the AA phases. With REC the moments (rho, u_x, u_y,
 // N_xx, N_xy) of every node are written to rec, laid out like the populations with five
 // entries per lattice row (row stride rec_rs).
-template <class S, int MODEL, int PH, bool REC, int NPT>
+template <class S, int MODEL, int PH, bool REC, int NPT, bool WT>
 __global__ void __launch_bounds__(kBlock)
 k_step(const S* src, S* dst, Geo geo, Coef<typename StorageTraits<S>::T> k,
        typename StorageTraits<S>::T* rec, int64_t rec_rs) {
@@ -235,7 +239,7 @@ k_step(const S* src, S* dst, Geo geo, Coef<typename StorageTraits<S>::T> k,
   const size_t rsb = size_t(geo.rs) * sizeof(S), psb = size_t(geo.ps) * sizeof(S);
   const char* sr[3] = {reinterpret_cast<const char*>(src) + ym * rsb, reinterpret_cast<const char*>(src) + y * rsb,
                        reinterpret_cast<const char*>(src) + yp * rsb};
-  // Stores through buffer descriptors of the three rows (cache policy kAuxStore).
+  // Stores through buffer descriptors of the three rows (cache policy kAuxStore<WT>).
   const RowRes dr[3] = {row_res(dst, rsb, ym), row_res(dst, rsb, y), row_res(dst, rsb, yp)};
 
   typename Tr::Raw gs[NPT][Q];
@@ -260,7 +264,8 @@ k_step(const S* src, S* dst, Geo geo, Coef<typename StorageTraits<S>::T> k,
     if constexpr (REC) {
       const RowRes rr = row_res(rec, size_t(rec_rs) * sizeof(T), y);
 #pragma unroll
-      for (int r = 0; r < NREC; ++r) stb<T>(rr, r * geo.ps * int(sizeof(T)), uint32_t(rp[n].p0) * uint32_t(sizeof(T)), rv[r]);
+      for (int r = 0; r < NREC; ++r)
+        stb<T, kAuxStore<WT>>(rr, r * geo.ps * int(sizeof(T)), uint32_t(rp[n].p0) * uint32_t(sizeof(T)), rv[r]);
     }
     static_for<0, Q>([&](auto I) {
       constexpr int i = decltype(I)::value;
@@ -268,7 +273,8 @@ k_step(const S* src, S* dst, Geo geo, Coef<typename StorageTraits<S>::T> k,
       constexpr int slot = (PH == PH_AA_EVEN) ? opp(i) : i;
       constexpr int dx = shift ? cx(i) : 0;
       constexpr int dy = shift ? cy(i) : 0;
-      stb<S>(dr[dy + 1], slot * int(psb), uint32_t(rp[n].template of<dx>()) * uint32_t(sizeof(S)), Tr::store(out[i]));
+      stb<S, kAuxStore<WT>>(dr[dy + 1], slot * int(psb), uint32_t(rp[n].template of<dx>()) * uint32_t(sizeof(S)),
+                            Tr::store(out[i]));
     });
   }
 }
@@ -367,7 +373,7 @@ template <> struct RotatedFuseLoop<float> : std::true_type {};
 
 // With REC the moments of both steps are recorded (rec1: first step, rec2: second step; the
 // layout and row stride rec_rs of k_step), by the interior wavefronts for the block's rows.
-template <class S, int MODEL, bool REC>
+template <class S, int MODEL, bool REC, bool WT>
 __global__ void __launch_bounds__((kFuseGroups + 2) * kLanes)
 k_step2(const S* __restrict__ src, S* __restrict__ dst, Geo geo, Coef<typename StorageTraits<S>::T> k,
         typename StorageTraits<S>::T* __restrict__ rec1, typename StorageTraits<S>::T* __restrict__ rec2,
@@ -415,7 +421,7 @@ k_step2(const S* __restrict__ src, S* __restrict__ dst, Geo geo, Coef<typename S
       if (interior && r >= y0 && r < y1) {
         const RowRes rr = row_res(rec1, size_t(rec_rs) * sizeof(T), r);
 #pragma unroll
-        for (int j = 0; j < NREC; ++j) stb<T>(rr, j * geo.ps * int(sizeof(T)), pb * uint32_t(sizeof(T)), rv[j]);
+        for (int j = 0; j < NREC; ++j) stb<T, kAuxStore<WT>>(rr, j * geo.ps * int(sizeof(T)), pb * uint32_t(sizeof(T)), rv[j]);
       }
     }
   };
@@ -433,11 +439,11 @@ k_step2(const S* __restrict__ src, S* __restrict__ dst, Geo geo, Coef<typename S
     if constexpr (REC) {
       const RowRes rr = row_res(rec2, size_t(rec_rs) * sizeof(T), yr);
 #pragma unroll
-      for (int j = 0; j < NREC; ++j) stb<T>(rr, j * geo.ps * int(sizeof(T)), pb * uint32_t(sizeof(T)), rv[j]);
+      for (int j = 0; j < NREC; ++j) stb<T, kAuxStore<WT>>(rr, j * geo.ps * int(sizeof(T)), pb * uint32_t(sizeof(T)), rv[j]);
     }
     const RowRes dr = row_res(dst, rsb, yr);
 #pragma unroll
-    for (int i = 0; i < Q; ++i) stb<S>(dr, i * psb, pb * uint32_t(sizeof(S)), Tr::store(out[i]));
+    for (int i = 0; i < Q; ++i) stb<S, kAuxStore<WT>>(dr, i * psb, pb * uint32_t(sizeof(S)), Tr::store(out[i]));
   };
   auto load = [&](const int r) { load_pulled<S>(src, geo, r, ra, gs); };
   auto load_plain = [&](const int r) { load_pulled<S, false>(src, geo, r, ra, gs); };
